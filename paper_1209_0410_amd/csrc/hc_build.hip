@@ -1,0 +1,333 @@
+// Index build (Alg. 1): per curve, the <key, id> list sorted by (key, id).
+//
+// The keys of one curve are encoded straight into the index buffer with ids in
+// ascending order, then sorted by a stable least-significant-digit radix sort
+// over the sixteen 8-bit digits of the 128-bit key.  Stability keeps equal keys
+// in id order, which gives the (key, id) order.  A digit that is the same for
+// every key (common: the data are small, so many high-order Hilbert bits are
+// zero) is skipped.  Finally the 64-ary sampled-key table the search descends
+// is extracted: level L holds key[j * 64^L].
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "hc_hilbert.h"
+
+namespace hc {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;   // 4096 keys per tile
+constexpr int kScanThreads = 1024;
+
+__device__ inline uint32_t key_digit(const Key &k, int d)
+{
+    return (uint32_t)((d < 8 ? (k.lo >> (8 * d)) : (k.hi >> (8 * (d - 8)))) & 0xFFu);
+}
+
+__device__ inline uint32_t lanes_below(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Keys of curve c for every row, ids ascending.
+__global__ __launch_bounds__(256) void k_encode_curve(IndexView v, uint32_t c, Key *keys,
+                                                      uint32_t *ids)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= v.n) return;
+    uint32_t coord[kDpc];
+    project16(v.db + i * kDim, v, c, coord);
+    keys[i] = hilbert_key16(coord);
+    ids[i] = (uint32_t)i;
+}
+
+// Histograms of all sixteen digits (hist[d * 256 + value]).
+__global__ __launch_bounds__(256) void k_digit_hist(const Key *keys, uint64_t n,
+                                                    uint32_t *hist)
+{
+    __shared__ uint32_t h[16 * 256];
+    for (int i = threadIdx.x; i < 16 * 256; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const Key k = keys[i];
+#pragma unroll
+        for (int d = 0; d < 16; d++) atomicAdd(&h[d * 256 + key_digit(k, d)], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 16 * 256; i += blockDim.x)
+        if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+// Per-tile counts of digit d: counts[value * ntiles + tile].
+__global__ __launch_bounds__(kSortThreads) void k_tile_hist(const Key *keys, uint64_t n,
+                                                            int d, uint32_t *counts,
+                                                            uint32_t ntiles)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+#pragma unroll 4
+    for (int r = 0; r < kSortItems; r++) {
+        const uint64_t e = base + (uint64_t)r * kSortThreads + threadIdx.x;
+        if (e < n) atomicAdd(&h[key_digit(keys[e], d)], 1u);
+    }
+    __syncthreads();
+    counts[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive prefix sum of a wave's values; *total receives the wave's sum.
+__device__ inline uint32_t wave_excl_scan(uint32_t v, uint32_t *total)
+{
+    const int lane = threadIdx.x & 63;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    *total = __shfl(x, 63, 64);
+    return x - v;
+}
+
+// In-place exclusive prefix sum of n values, one block of kScanThreads.
+__global__ __launch_bounds__(kScanThreads) void k_scan_excl(uint32_t *a, uint64_t n)
+{
+    __shared__ uint32_t wsum[kScanThreads / 64];
+    __shared__ uint32_t carry_s;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    if (tid == 0) carry_s = 0;
+    __syncthreads();
+    for (uint64_t base = 0; base < n; base += (uint64_t)kScanThreads * 4) {
+        uint32_t v[4];
+        uint32_t s = 0;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint64_t i = base + (uint64_t)tid * 4 + j;
+            v[j] = i < n ? a[i] : 0u;
+            s += v[j];
+        }
+        uint32_t wt;
+        uint32_t ex = wave_excl_scan(s, &wt);
+        if (lane == 0) wsum[wave] = wt;
+        __syncthreads();
+        if (wave == 0) {
+            uint32_t t = lane < kScanThreads / 64 ? wsum[lane] : 0u;
+            uint32_t tot;
+            uint32_t e = wave_excl_scan(t, &tot);
+            if (lane < kScanThreads / 64) wsum[lane] = e;
+        }
+        __syncthreads();
+        uint32_t run = carry_s + wsum[wave] + ex;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint64_t i = base + (uint64_t)tid * 4 + j;
+            if (i < n) a[i] = run;
+            run += v[j];
+        }
+        __syncthreads();
+        if (tid == kScanThreads - 1) carry_s = run;
+        __syncthreads();
+    }
+}
+
+// Stable scatter of one digit pass.  Within a tile, keys are visited in order:
+// rounds of 256 consecutive keys, lanes in order, waves in order; a wave ranks
+// its lanes among equal digits with ballots.
+__global__ __launch_bounds__(kSortThreads) void k_scatter(const Key *src, const uint32_t *src_ids,
+                                                          Key *dst, uint32_t *dst_ids,
+                                                          uint64_t n, int d,
+                                                          const uint32_t *offsets,
+                                                          uint32_t ntiles)
+{
+    constexpr int kWaves = kSortThreads / 64;
+    __shared__ uint32_t wave_cnt[kWaves][256];
+    __shared__ uint32_t run[256];
+    const int tid = threadIdx.x, wave = tid >> 6;
+    run[tid] = offsets[(uint64_t)tid * ntiles + blockIdx.x];
+#pragma unroll
+    for (int w = 0; w < kWaves; w++) wave_cnt[w][tid] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortItems; r++) {
+        const uint64_t e = base + (uint64_t)r * kSortThreads + tid;
+        const bool valid = e < n;
+        Key k = {0, 0};
+        uint32_t id = 0;
+        if (valid) {
+            k = src[e];
+            id = src_ids[e];
+        }
+        const uint32_t dig = valid ? key_digit(k, d) : 0u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            const bool bit = (dig >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t rank = lanes_below(peers);
+        if (valid && rank == 0) wave_cnt[wave][dig] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[dig] + rank;
+            for (int w = 0; w < wave; w++) pos += wave_cnt[w][dig];
+            dst[pos] = k;
+            dst_ids[pos] = id;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; w++) {
+            add += wave_cnt[w][tid];
+            wave_cnt[w][tid] = 0;
+        }
+        run[tid] += add;
+        __syncthreads();
+    }
+}
+
+// Level L of the sampled-key table: out[j] = leaf[j * stride].
+__global__ __launch_bounds__(256) void k_sample_keys(const Key *leaf, uint64_t stride,
+                                                     Key *out, uint64_t len)
+{
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < len) out[j] = leaf[j * stride];
+}
+
+struct BuildScratch {
+    Key *keys;
+    uint32_t *ids;
+    uint32_t *hist;      // 16 * 256
+    uint32_t *counts;    // 256 * ntiles
+    size_t total;
+};
+
+static BuildScratch build_scratch_layout(uint64_t n, uint8_t *base)
+{
+    const uint64_t ntiles = (n + kSortTile - 1) / kSortTile;
+    BuildScratch s{};
+    size_t off = 0;
+    s.keys = (Key *)(base + off);
+    off = align256(off + sizeof(Key) * n);
+    s.ids = (uint32_t *)(base + off);
+    off = align256(off + sizeof(uint32_t) * n);
+    s.hist = (uint32_t *)(base + off);
+    off = align256(off + sizeof(uint32_t) * 16 * 256);
+    s.counts = (uint32_t *)(base + off);
+    off = align256(off + sizeof(uint32_t) * 256 * ntiles);
+    s.total = off;
+    return s;
+}
+
+static uint32_t blocks_for(uint64_t n, uint32_t per)
+{
+    return (uint32_t)((n + per - 1) / per);
+}
+
+static hc_status sort_curve(const IndexView &v, uint32_t c, Key *keys, uint32_t *ids,
+                            const BuildScratch &s, hipStream_t st)
+{
+    const uint64_t n = v.n;
+    const uint32_t ntiles = blocks_for(n, kSortTile);
+    hipLaunchKernelGGL(k_encode_curve, dim3(blocks_for(n, 256)), dim3(256), 0, st, v, c,
+                       keys, ids);
+    hipLaunchKernelGGL(k_fill_u32, dim3(16), dim3(256), 0, st, s.hist, (uint64_t)16 * 256,
+                       0u);
+    const uint32_t hblocks = (uint32_t)std::min<uint64_t>(1024, blocks_for(n, 256));
+    hipLaunchKernelGGL(k_digit_hist, dim3(hblocks), dim3(256), 0, st, keys, n, s.hist);
+    std::vector<uint32_t> hist(16 * 256);
+    if (hipMemcpyAsync(hist.data(), s.hist, sizeof(uint32_t) * hist.size(),
+                       hipMemcpyDeviceToHost, st) != hipSuccess)
+        return HC_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return HC_ERR_HIP;
+
+    Key *src = keys, *dst = s.keys;
+    uint32_t *src_ids = ids, *dst_ids = s.ids;
+    for (int d = 0; d < 16; d++) {
+        bool trivial = false;
+        for (int b = 0; b < 256; b++)
+            if (hist[d * 256 + b] == n) trivial = true;
+        if (trivial) continue;
+        hipLaunchKernelGGL(k_tile_hist, dim3(ntiles), dim3(kSortThreads), 0, st, src, n, d,
+                           s.counts, ntiles);
+        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(kScanThreads), 0, st, s.counts,
+                           (uint64_t)256 * ntiles);
+        hipLaunchKernelGGL(k_scatter, dim3(ntiles), dim3(kSortThreads), 0, st, src, src_ids,
+                           dst, dst_ids, n, d, s.counts, ntiles);
+        std::swap(src, dst);
+        std::swap(src_ids, dst_ids);
+    }
+    if (src != keys) {
+        if (hipMemcpyAsync(keys, src, sizeof(Key) * n, hipMemcpyDeviceToDevice, st) !=
+                hipSuccess ||
+            hipMemcpyAsync(ids, src_ids, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice,
+                           st) != hipSuccess)
+            return HC_ERR_HIP;
+    }
+    uint64_t stride = 1;
+    for (uint32_t l = 1; l <= v.levels; l++) {
+        stride *= kFan;
+        hipLaunchKernelGGL(k_sample_keys, dim3(blocks_for(v.len[l], 256)), dim3(256), 0, st,
+                           (const Key *)keys, stride, (Key *)v.lvl[c][l], v.len[l]);
+    }
+    return last_hip();
+}
+
+}  // namespace hc
+
+using namespace hc;
+
+extern "C" {
+
+hc_status hc_index_bytes(const hc_params *p, uint64_t n, size_t *index_bytes,
+                         size_t *build_scratch_bytes)
+{
+    hc_status st = check_params(p, nullptr, nullptr);
+    if (st != HC_OK) return st;
+    if (n == 0) return HC_ERR_INVALID;
+    if (n >= 0xFFFFFFFFull) return HC_ERR_UNSUPPORTED;
+    if (index_bytes) *index_bytes = make_layout(p->curves, n).total;
+    if (build_scratch_bytes) *build_scratch_bytes = build_scratch_layout(n, nullptr).total;
+    return HC_OK;
+}
+
+hc_status hc_build_index(const hc_params *p, const uint8_t *d_db, uint64_t n, void *d_index,
+                         size_t index_bytes, void *d_scratch, size_t scratch_bytes,
+                         hc_stream stream, hc_index **out)
+{
+    if (!out) return HC_ERR_INVALID;
+    hc_index *h = new (std::nothrow) hc_index;
+    if (!h) return HC_ERR_INVALID;
+    hc_status st = fill_view(p, d_db, n, d_index, index_bytes, &h->v);
+    if (st == HC_OK && (!d_scratch || ((uintptr_t)d_scratch & 255))) st = HC_ERR_INVALID;
+    BuildScratch s{};
+    if (st == HC_OK) {
+        s = build_scratch_layout(n, (uint8_t *)d_scratch);
+        if (scratch_bytes < s.total) st = HC_ERR_SIZE;
+    }
+    for (uint32_t c = 0; st == HC_OK && c < h->v.curves; c++)
+        st = sort_curve(h->v, c, (Key *)h->v.lvl[c][0], (uint32_t *)h->v.ids[c], s,
+                        (hipStream_t)stream);
+    if (st != HC_OK) {
+        delete h;
+        return st;
+    }
+    h->base = d_index;
+    h->bytes = index_bytes;
+    *out = h;
+    return HC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,104 @@
+// Internal definitions shared by the library's translation units (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hypercurves.h"
+
+namespace hc {
+
+constexpr int kDim = 128;          // bytes per vector
+constexpr int kDpc = 16;           // dims per curve
+constexpr int kMaxCurves = 8;
+constexpr int kFan = 64;           // fan-out of the sampled-key table = wave size
+constexpr int kMaxLevels = 6;      // 64^6 > 2^32 rows
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+constexpr uint64_t kNone = ~0ull;  // packed (dist << 32 | id) of an empty slot
+
+struct Key {                       // 128-bit key, compared as (hi, lo)
+    uint64_t hi, lo;
+};
+
+// Device view of one index, passed by value to kernels.
+struct IndexView {
+    const uint8_t *db;
+    uint64_t n;
+    uint32_t curves;
+    uint32_t levels;                          // D: top table is level D
+    uint64_t len[kMaxLevels + 1];             // entries of level L (len[0] = n)
+    const Key *lvl[kMaxCurves][kMaxLevels + 1];   // lvl[c][0] = sorted keys
+    const uint32_t *ids[kMaxCurves];
+    uint16_t perm[kMaxCurves * kDpc];
+    uint32_t identity;                        // perm is 16c + j
+};
+
+}  // namespace hc
+
+struct hc_index {
+    hc::IndexView v;
+    void *base;
+    size_t bytes;
+};
+
+namespace hc {
+
+// Layout of the index buffer: per curve, keys[n], ids[n], then levels 1..D;
+// every array starts on a 256-byte boundary.
+struct Layout {
+    uint32_t levels;
+    uint64_t len[kMaxLevels + 1];
+    size_t keys_off[kMaxCurves], ids_off[kMaxCurves];
+    size_t lvl_off[kMaxCurves][kMaxLevels + 1];
+    size_t total;
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+inline Layout make_layout(uint32_t curves, uint64_t n)
+{
+    Layout L{};
+    uint32_t D = 0;
+    L.len[0] = n;
+    while (L.len[D] > (uint64_t)kFan && D < kMaxLevels) {
+        L.len[D + 1] = (L.len[D] + kFan - 1) / kFan;
+        D++;
+    }
+    L.levels = D;
+    size_t off = 0;
+    for (uint32_t c = 0; c < curves; c++) {
+        L.keys_off[c] = off;
+        L.lvl_off[c][0] = off;
+        off = align256(off + sizeof(Key) * n);
+        L.ids_off[c] = off;
+        off = align256(off + sizeof(uint32_t) * n);
+        for (uint32_t l = 1; l <= D; l++) {
+            L.lvl_off[c][l] = off;
+            off = align256(off + sizeof(Key) * L.len[l]);
+        }
+    }
+    L.total = off;
+    return L;
+}
+
+hc_status check_params(const hc_params *p, uint16_t *perm_out, uint32_t *identity);
+hc_status fill_view(const hc_params *p, const uint8_t *d_db, uint64_t n, void *d_index,
+                    size_t index_bytes, IndexView *v);
+
+// Launch helpers -----------------------------------------------------------
+
+inline hc_status last_hip()
+{
+    return hipGetLastError() == hipSuccess ? HC_OK : HC_ERR_HIP;
+}
+
+// Query keys for the search kernels: keys[q*curves + c].
+hc_status encode_rows(const IndexView &v, const uint8_t *rows, uint64_t nrows, Key *keys,
+                      hipStream_t s);
+
+__device__ inline bool key_less(const Key &a, const Key &b)
+{
+    return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo);
+}
+
+}  // namespace hc

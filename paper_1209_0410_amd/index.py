@@ -1,0 +1,182 @@
+"""Index and search over device tensors, through the C ABI.
+
+PyTorch supplies device memory and the current HIP stream; every step of the
+index build and of the search runs in libhypercurves.so.
+"""
+import ctypes as ct
+
+import torch
+
+from . import capi
+
+
+def _ptr(t):
+    return ct.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check_rows(x, name):
+    if not (x.is_cuda and x.dtype == torch.uint8 and x.dim() == 2 and x.shape[1] == 128
+            and x.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous (n, 128) uint8 CUDA tensor")
+    if x.data_ptr() % 16:
+        raise ValueError(f"{name} must be 16-byte aligned")
+
+
+def _empty_bytes(nbytes, device):
+    t = torch.empty(max(int(nbytes), 256) + 256, dtype=torch.uint8, device=device)
+    off = (-t.data_ptr()) % 256
+    return t[off:off + max(int(nbytes), 256)]
+
+
+def encode_keys(rows, curves=8, perm=None):
+    """Hilbert keys of every row and curve: int64 tensor (rows, curves, 2) of {hi, lo}."""
+    _check_rows(rows, "rows")
+    p, keep = capi.make_params(curves=curves, perm=perm)
+    out = torch.empty((rows.shape[0], curves, 2), dtype=torch.int64, device=rows.device)
+    capi.call("hc_encode_keys", ct.byref(p), _ptr(rows), rows.shape[0], _ptr(out), _stream())
+    del keep
+    return out
+
+
+class Index:
+    """Alg. 1 index of a resident uint8 database (n, 128) on one GPU."""
+
+    def __init__(self, db, curves=8, perm=None):
+        _check_rows(db, "db")
+        self.db = db
+        self.n = db.shape[0]
+        self.curves = curves
+        self.perm = None if perm is None else [int(x) for x in perm]
+        self._p, self._keep = capi.make_params(curves=curves, perm=self.perm)
+        ib, sb = ct.c_size_t(), ct.c_size_t()
+        capi.call("hc_index_bytes", ct.byref(self._p), self.n, ct.byref(ib), ct.byref(sb))
+        self.index_bytes = ib.value
+        self.buf = _empty_bytes(ib.value, db.device)
+        scratch = _empty_bytes(sb.value, db.device)
+        h = ct.c_void_p()
+        capi.call("hc_build_index", ct.byref(self._p), _ptr(db), self.n, _ptr(self.buf),
+                  ib.value, _ptr(scratch), sb.value, _stream(), ct.byref(h))
+        self.handle = h
+        self._scratch = None
+        torch.cuda.current_stream().synchronize()
+        del scratch
+
+    @classmethod
+    def attach(cls, db, buf, curves=8, perm=None):
+        """Handle over an index buffer restored from a previous build."""
+        self = cls.__new__(cls)
+        _check_rows(db, "db")
+        self.db, self.n, self.curves = db, db.shape[0], curves
+        self.perm = None if perm is None else [int(x) for x in perm]
+        self._p, self._keep = capi.make_params(curves=curves, perm=self.perm)
+        self.buf = buf
+        self.index_bytes = buf.numel()
+        h = ct.c_void_p()
+        capi.call("hc_index_attach", ct.byref(self._p), _ptr(db), self.n, _ptr(buf),
+                  buf.numel(), ct.byref(h))
+        self.handle = h
+        self._scratch = None
+        return self
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                capi.load().hc_index_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    # -- helpers --------------------------------------------------------------
+    def scratch(self, nq):
+        sz = ct.c_size_t()
+        capi.call("hc_search_scratch_bytes", self.handle, nq, ct.byref(sz))
+        if self._scratch is None or self._scratch.numel() < sz.value:
+            self._scratch = _empty_bytes(sz.value, self.db.device)
+        return self._scratch
+
+    def curve(self, c):
+        """(keys int64 (n, 2) of {hi, lo}, ids int32 (n,)) views of curve c's list."""
+        kp, ip = ct.c_void_p(), ct.c_void_p()
+        capi.call("hc_index_curve", self.handle, c, ct.byref(kp), ct.byref(ip))
+        base = self.buf.data_ptr()
+        ko = (kp.value - base)
+        io = (ip.value - base)
+        keys = self.buf[ko:ko + 16 * self.n].view(torch.int64).view(self.n, 2)
+        ids = self.buf[io:io + 4 * self.n].view(torch.int32)
+        return keys, ids
+
+    # -- search ---------------------------------------------------------------
+    def search(self, queries, k, w=64, w_per_query=None, out=None, scratch=None):
+        """Alg. 2: (ids, dists) int32 tensors (nq, k); uint32 values, 0xFFFFFFFF = empty."""
+        _check_rows(queries, "queries")
+        nq = queries.shape[0]
+        if out is None:
+            ids = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
+            dists = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
+        else:
+            ids, dists = out
+        sc = scratch if scratch is not None else self.scratch(nq)
+        wp = None
+        if w_per_query is not None:
+            assert w_per_query.dtype == torch.int32 and w_per_query.is_cuda
+            wp = _ptr(w_per_query)
+        capi.call("hc_search_batch", self.handle, _ptr(queries), nq, k, int(w or 0), wp,
+                  _ptr(ids), _ptr(dists), _ptr(sc), sc.numel(), _stream())
+        return ids, dists
+
+    def encode_queries(self, queries, scratch):
+        """First launch of search(): query keys into `scratch`."""
+        capi.call("hc_encode_queries", self.handle, _ptr(queries), queries.shape[0],
+                  _ptr(scratch), scratch.numel(), _stream())
+
+    def search_encoded(self, queries, k, w, out, scratch, w_per_query=None):
+        """Second launch of search(): keys already in `scratch`."""
+        ids, dists = out
+        wp = _ptr(w_per_query) if w_per_query is not None else None
+        capi.call("hc_search_encoded", self.handle, _ptr(queries), queries.shape[0], k,
+                  int(w or 0), wp, _ptr(ids), _ptr(dists), _ptr(scratch), scratch.numel(),
+                  _stream())
+        return ids, dists
+
+    def positions(self, queries):
+        _check_rows(queries, "queries")
+        nq = queries.shape[0]
+        out = torch.empty((nq, self.curves), dtype=torch.int32, device=queries.device)
+        sc = self.scratch(nq)
+        capi.call("hc_positions", self.handle, _ptr(queries), nq, _ptr(out), _ptr(sc),
+                  sc.numel(), _stream())
+        return out
+
+    def candidates(self, queries, w=64, w_per_query=None, stride=None):
+        """(counts int32 (nq,), ids int32 (nq, stride)); row q holds counts[q] ids, unordered."""
+        _check_rows(queries, "queries")
+        nq = queries.shape[0]
+        if stride is None:
+            stride = 16 * int(w)
+        counts = torch.empty(nq, dtype=torch.int32, device=queries.device)
+        ids = torch.empty((nq, max(stride, 1)), dtype=torch.int32, device=queries.device)
+        sc = self.scratch(nq)
+        wp = _ptr(w_per_query) if w_per_query is not None else None
+        capi.call("hc_candidates", self.handle, _ptr(queries), nq, int(w), wp, _ptr(counts),
+                  _ptr(ids), stride, _ptr(sc), sc.numel(), _stream())
+        return counts, ids
+
+
+def brute_force(db, queries, k):
+    """Eq. (3) exact kNN on the GPU: (ids, dists) int32 tensors (nq, k)."""
+    _check_rows(db, "db")
+    _check_rows(queries, "queries")
+    nq = queries.shape[0]
+    sz = ct.c_size_t()
+    capi.call("hc_brute_force_scratch_bytes", db.shape[0], nq, k, ct.byref(sz))
+    sc = _empty_bytes(sz.value, db.device)
+    ids = torch.empty((nq, k), dtype=torch.int32, device=db.device)
+    dists = torch.empty((nq, k), dtype=torch.int32, device=db.device)
+    capi.call("hc_brute_force", _ptr(db), db.shape[0], _ptr(queries), nq, k, _ptr(ids),
+              _ptr(dists), _ptr(sc), sc.numel(), _stream())
+    return ids, dists

@@ -1,0 +1,83 @@
+"""The C-ABI library loads and exports every entry point the header declares;
+argument validation happens before any launch (no GPU needed)."""
+import ctypes as ct
+import os
+import re
+
+import pytest
+
+from paper_1209_0410_amd import capi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hypercurves.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(capi.LIB_PATH):
+        from paper_1209_0410_amd import build
+        build.build()
+    return capi.load()
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hc_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for must in ["hc_build_index", "hc_search_batch", "hc_index_bytes", "hc_status_str",
+                 "hc_positions", "hc_candidates", "hc_encode_keys", "hc_brute_force"]:
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared():
+        assert hasattr(lib, name), name
+        assert name == "hc_status_str" or name in capi.SIGNATURES, name
+
+
+def test_status_strings(lib):
+    assert capi.status_str(0) == "ok"
+    assert capi.status_str(-2) == "buffer too small"
+    assert capi.status_str(-4) == "unsupported shape"
+
+
+def test_index_bytes_validation(lib):
+    p, _ = capi.make_params()
+    ib, sb = ct.c_size_t(), ct.c_size_t()
+    assert lib.hc_index_bytes(ct.byref(p), 1000, ct.byref(ib), ct.byref(sb)) == 0
+    # 8 curves x (16 B key + 4 B id) per row, plus the sampled-key table
+    assert ib.value >= 8 * 20 * 1000
+    assert lib.hc_index_bytes(ct.byref(p), 0, ct.byref(ib), ct.byref(sb)) == capi.HC_ERR_INVALID
+    bad, _ = capi.make_params(dim=64)
+    assert lib.hc_index_bytes(ct.byref(bad), 10, ct.byref(ib), None) == capi.HC_ERR_UNSUPPORTED
+    bad, _ = capi.make_params(curves=9)
+    assert lib.hc_index_bytes(ct.byref(bad), 10, ct.byref(ib), None) == capi.HC_ERR_UNSUPPORTED
+    bad, keep = capi.make_params(perm=[200] * 128)
+    assert lib.hc_index_bytes(ct.byref(bad), 10, ct.byref(ib), None) == capi.HC_ERR_INVALID
+
+
+def test_search_rejects_bad_arguments_before_launch(lib):
+    null = ct.c_void_p(0)
+    # null handle, k = 0, k too large, null outputs: all rejected synchronously
+    assert lib.hc_search_batch(null, null, 1, 10, 8, null, null, null, null, 0, null) != 0
+    assert lib.hc_search_batch(null, null, 1, 0, 8, null, null, null, null, 0, null) == \
+        capi.HC_ERR_INVALID
+    assert lib.hc_search_batch(null, null, 1, capi.HC_K_MAX + 1, 8, null, null, null, null,
+                               0, null) == capi.HC_ERR_INVALID
+    p, _ = capi.make_params()
+    out = ct.c_void_p()
+    assert lib.hc_build_index(ct.byref(p), null, 10, null, 0, null, 0, null,
+                              ct.byref(out)) == capi.HC_ERR_INVALID
+    assert lib.hc_index_destroy(null) == capi.HC_ERR_INVALID
+
+
+def test_brute_force_validation(lib):
+    sz = ct.c_size_t()
+    assert lib.hc_brute_force_scratch_bytes(1000, 10, 10, ct.byref(sz)) == 0
+    assert sz.value >= 10 * 10 * 8
+    assert lib.hc_brute_force_scratch_bytes(1000, 10, 17, ct.byref(sz)) == \
+        capi.HC_ERR_UNSUPPORTED

@@ -1,0 +1,162 @@
+"""GPU parity: every step of the HIP search path, called through the C ABI,
+against the CPU oracle on the same seeded inputs.  Integer work, so the bar
+is bit-exact: keys, sorted lists, positions, candidate sets, distances,
+top-k ids and distances (ties by id)."""
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+U32 = 0xFFFFFFFF
+
+
+def u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    return torch
+
+
+@pytest.fixture(scope="module")
+def c1(oracle, torch_mod):
+    """Plain method, tiny: N = 100,000, Q = 1,000 (mixture seeds 1 and 2)."""
+    from paper_1209_0410_amd import datagen
+    from paper_1209_0410_amd.index import Index
+    db = datagen.make_db(100_000)
+    q = datagen.make_queries(1000)
+    dev = torch_mod.device("cuda:0")
+    gdb = torch_mod.from_numpy(db).to(dev)
+    gq = torch_mod.from_numpy(q).to(dev)
+    print(f"[c1] building GPU index n={db.shape[0]}", flush=True)
+    gix = Index(gdb)
+    oix = oracle.Index(db)
+    return dict(db=db, q=q, gdb=gdb, gq=gq, gix=gix, oix=oix)
+
+
+def test_encode_keys_bit_exact(c1, oracle, torch_mod):
+    from paper_1209_0410_amd.index import encode_keys
+    keys = u64(encode_keys(c1["gdb"]))                   # (n, 8, 2) {hi, lo}
+    hi, lo = oracle.keys(c1["db"], oracle.Params())
+    assert (keys[:, :, 0] == hi).all() and (keys[:, :, 1] == lo).all()
+
+
+def test_encode_keys_random_points(oracle, torch_mod):
+    """Uniform random bytes (all 256 values per coordinate) and extremes."""
+    from paper_1209_0410_amd.index import encode_keys
+    rng = np.random.default_rng(7)
+    rows = rng.integers(0, 256, size=(50_000, 128), dtype=np.uint8)
+    rows[0] = 0
+    rows[1] = 255
+    rows[2] = np.arange(128) % 256
+    g = u64(encode_keys(torch_mod.from_numpy(rows).cuda()))
+    hi, lo = oracle.keys(rows, oracle.Params())
+    assert (g[:, :, 0] == hi).all() and (g[:, :, 1] == lo).all()
+
+
+def test_sorted_lists_bit_exact(c1):
+    gix, oix = c1["gix"], c1["oix"]
+    for c in range(8):
+        keys, ids = gix.curve(c)
+        k = u64(keys)
+        assert (k[:, 0] == oix.hi[c]).all() and (k[:, 1] == oix.lo[c]).all(), c
+        assert (u32(ids) == oix.ids[c]).all(), c
+
+
+def test_positions_bit_exact(c1):
+    pos = u32(c1["gix"].positions(c1["gq"]))
+    assert (pos == c1["oix"].positions(c1["q"])).all()
+
+
+@pytest.mark.parametrize("w", [1, 16, 64, 256])
+def test_candidate_sets_bit_exact(c1, w):
+    counts, ids = c1["gix"].candidates(c1["gq"][:300], w)
+    counts = u32(counts)
+    ids = u32(ids)
+    ref = c1["oix"].candidates(c1["q"][:300], w)
+    for i, r in enumerate(ref):
+        assert counts[i] == len(r)
+        assert (np.sort(ids[i, :counts[i]]) == r).all()
+
+
+@pytest.mark.parametrize("k,w", [(10, 64), (1, 16), (10, 1), (16, 256), (17, 64),
+                                 (100, 64), (256, 40), (10, 300), (10, 600), (5, 2000)])
+def test_search_bit_exact(c1, k, w):
+    nq = 1000 if w <= 300 else 200
+    ids, d = c1["gix"].search(c1["gq"][:nq], k, w)
+    rid, rd = c1["oix"].search(c1["q"][:nq], k, w)
+    assert (u32(ids) == rid).all()
+    assert (u32(d) == rd).all()
+
+
+def test_per_query_w_bit_exact(c1, torch_mod):
+    rng = np.random.default_rng(3)
+    w = rng.integers(0, 400, size=1000).astype(np.uint32)
+    w[:5] = [0, 1, 2, 700, 5000]
+    gw = torch_mod.from_numpy(w.view(np.int32)).cuda()
+    for hint in [0, 32, 256]:
+        ids, d = c1["gix"].search(c1["gq"], 10, hint, w_per_query=gw)
+        rid, rd = c1["oix"].search(c1["q"], 10, w)
+        assert (u32(ids) == rid).all() and (u32(d) == rd).all(), hint
+
+
+def test_brute_force_bit_exact(c1, oracle):
+    from paper_1209_0410_amd.index import brute_force
+    ids, d = brute_force(c1["gdb"], c1["gq"][:200], 10)
+    rid, rd = oracle.brute_force(c1["db"], c1["q"][:200], 10)
+    assert (u32(ids) == rid).all() and (u32(d) == rd).all()
+
+
+def test_deterministic_and_batch_independent(c1):
+    gix, gq = c1["gix"], c1["gq"]
+    a_ids, a_d = gix.search(gq, 10, 64)
+    b_ids, b_d = gix.search(gq, 10, 64)
+    assert (u32(a_ids) == u32(b_ids)).all() and (u32(a_d) == u32(b_d)).all()
+    alone_ids, alone_d = gix.search(gq[17:18].contiguous(), 10, 64)
+    assert (u32(alone_ids)[0] == u32(a_ids)[17]).all()
+
+
+@pytest.mark.parametrize("n", [1, 7, 64, 65, 1000, 4097, 65537])
+def test_small_shapes_bit_exact(oracle, torch_mod, n):
+    from paper_1209_0410_amd import datagen
+    from paper_1209_0410_amd.index import Index
+    db = datagen.make_rows(n, 11)
+    if n > 100:
+        db[50::50] = db[3]                     # forced duplicate keys and distance ties
+    q = datagen.make_rows(300, 12)
+    q[0] = 0
+    q[1] = 255
+    q[2] = db[min(3, n - 1)]
+    print(f"[small] n={n}", flush=True)
+    gix = Index(torch_mod.from_numpy(db).cuda())
+    oix = oracle.Index(db)
+    for c in range(8):
+        keys, ids = gix.curve(c)
+        assert (u32(ids) == oix.ids[c]).all()
+    gq = torch_mod.from_numpy(q).cuda()
+    assert (u32(gix.positions(gq)) == oix.positions(q)).all()
+    for k, w in [(10, 1), (10, 8), (20, 64), (3, n)]:
+        ids, d = gix.search(gq, k, w)
+        rid, rd = oix.search(q, k, w)
+        assert (u32(ids) == rid).all() and (u32(d) == rd).all(), (k, w)
+
+
+def test_full_window_is_exact_knn(oracle, torch_mod):
+    from paper_1209_0410_amd import datagen
+    from paper_1209_0410_amd.index import Index
+    db = datagen.make_rows(3000, 21)
+    db[100:110] = db[7]
+    q = datagen.make_rows(100, 22)
+    gix = Index(torch_mod.from_numpy(db).cuda())
+    ids, d = gix.search(torch_mod.from_numpy(q).cuda(), 10, 3000)
+    rid, rd = oracle.brute_force(db, q, 10)
+    assert (u32(ids) == rid).all() and (u32(d) == rd).all()
