@@ -1,21 +1,28 @@
-// Multicurves search (Alg. 2) as one fused kernel per batch, gfx950.
+// Multicurves search (Alg. 2), gfx950.
 //
-// One workgroup per query:
-//  1. locate the query key in each curve's sorted list (count of keys < qkey)
-//     by descending the 64-ary sampled-key table: at every level one wave
-//     loads 64 consecutive keys (1 KiB, coalesced) and a ballot counts how
-//     many are below the query key; all curves of a wave descend together;
-//  2. window: w list entries on each side of that position (Alg. 2, the
-//     "probe-depth closest" entries, read as the half-list model of Sec. 4.2);
-//  3. union of the windows' ids as a set: an open-addressing hash in LDS;
-//  4. exact squared Euclidean distance of each distinct candidate (Eq. 2):
-//     8 lanes read one 128-byte row with 16-byte loads, dot4 integer
-//     arithmetic, a 3-step lane-xor reduction;
-//  5. the k nearest by (distance, id): each lane keeps a sorted list in
-//     registers; the wave then pops its global minimum k times.  For k > 16
-//     the distances go to LDS and are bitonic-sorted instead.
-// When the union is larger than the LDS chunk, steps 3-5 run per chunk and
-// the chunk results are merged, dropping repeated ids.
+// Search kernel (k_stream): one wavefront per query, no LDS for candidates.
+//  1. locate the query key in every curve's sorted list (the number of keys
+//     below it) by descending the 64-ary sampled-key table: at each level the
+//     wave loads 64 consecutive keys (1 KiB, coalesced) for all curves at once
+//     and a ballot counts those below the query key;
+//  2. window: w list entries on each side of that place (Alg. 2's "depth
+//     closest" entries, read as the half-list model of Sec. 4.2), clamped to
+//     the list ends; the windows of all curves are streamed as one sequence;
+//  3-4. per step the wave takes 64 window slots: one coalesced load of 64 ids,
+//     then 8 lanes read each 128-byte row with 16-byte loads, dot4 integer
+//     arithmetic gives the exact squared distance (Eq. 2), reduced over the 8
+//     lanes with lane-xor shuffles;
+//  5. top-k by (distance, id) over the union taken as a set: every lane keeps
+//     a sorted register list that refuses a key it already holds, and the wave
+//     pops its minimum k times, every lane holding that key popping it, so an
+//     id met in several windows counts once.  For k > 16 candidates below the
+//     current k-th distinct key collect in an LDS buffer that is bitonic-sorted
+//     and merged (dropping repeats) whenever it fills.
+// An id found in several windows is read again each time; at 10^7 rows this
+// is 0.2% of the rows (w = 64), less than a hash of the union would cost.
+//
+// Set kernel (k_sets): the same key location, then the union of the windows
+// built explicitly in an LDS hash -- the positions and candidate-set exports.
 #include <string.h>
 
 #include <algorithm>
@@ -24,10 +31,10 @@
 
 namespace hc {
 
-constexpr int kKR = 16;                 // register list length (k <= 16 path)
-constexpr uint32_t kMaxChunk = 4096;    // slots per chunk (LDS: 12 B per slot)
-
-enum { MODE_SEARCH = 0, MODE_POS = 1, MODE_CAND = 2 };
+constexpr int kKR = 16;                 // longest register list (k <= 16)
+constexpr int kBuf = 1024;              // LDS buffer of the k > 16 path
+constexpr uint32_t kMaxSetSlots = 4096; // union capacity of the set kernel
+constexpr int kIdBatch = 16;            // set kernel: ids loaded before inserting
 
 struct SearchArgs {
     IndexView v;
@@ -36,11 +43,11 @@ struct SearchArgs {
     uint32_t nq, k, w_fixed;
     const uint32_t *d_w;
     uint32_t *out_ids, *out_dists;
-    uint32_t *out_pos;         // MODE_POS: [q][curves]
-    uint32_t *out_counts;      // MODE_CAND
+    uint32_t *out_pos;         // positions export: [q][curves]
+    uint32_t *out_counts;      // candidates export
     uint32_t *out_cand;
     uint32_t cand_stride;
-    uint32_t cs_log2;          // chunk capacity = 1 << cs_log2 slots
+    uint32_t cs_log2;          // set kernel: union capacity = 1 << cs_log2
 };
 
 __device__ inline uint32_t lanes_below64(uint64_t mask)
@@ -67,7 +74,7 @@ __device__ inline uint64_t wave_min_u64(uint64_t v)
 }
 
 // Sum over 16 bytes of (q - x)^2 = q.q + x.x - 2 q.x with 4-byte dot products
-// (all terms are exact in uint32).
+// (every term is exact in uint32).
 __device__ inline uint32_t sqdist16(const uint4 &q, uint32_t qq, const uint4 &x)
 {
     uint32_t xx = __builtin_amdgcn_udot4(x.x, x.x, 0u, false);
@@ -81,129 +88,317 @@ __device__ inline uint32_t sqdist16(const uint4 &q, uint32_t qq, const uint4 &x)
     return qq + xx - 2u * qx;
 }
 
-// Inserts x into an ascending register list (unrolled: static indexing only).
-__device__ inline void list_insert(uint64_t (&L)[kKR], uint64_t x)
+// Inserts x into an ascending register list unless the list holds it already
+// (unrolled: static register indexing only).
+template <int KR>
+__device__ inline void insert_distinct(uint64_t (&L)[KR], uint64_t x)
 {
-    if (x < L[kKR - 1]) {
+    if (x < L[KR - 1]) {
+        bool dup = false;
 #pragma unroll
-        for (int i = kKR - 1; i > 0; i--)
-            L[i] = x < L[i - 1] ? L[i - 1] : (x < L[i] ? x : L[i]);
-        L[0] = x < L[0] ? x : L[0];
-    }
-}
-
-// Merges two ascending lists of k packed keys (kNone = empty) into out,
-// keeping the first k distinct keys.  Run by one thread.
-__device__ inline void merge_distinct(const uint64_t *a, const uint64_t *b, uint32_t k,
-                                      uint64_t *out)
-{
-    uint32_t i = 0, j = 0;
-    for (uint32_t o = 0; o < k; o++) {
-        const uint64_t x = i < k ? a[i] : kNone;
-        const uint64_t y = j < k ? b[j] : kNone;
-        if (x < y) {
-            out[o] = x;
-            i++;
-        } else if (y < x) {
-            out[o] = y;
-            j++;
-        } else {
-            out[o] = x;   // equal: the same candidate seen in two chunks
-            i++;
-            j++;
+        for (int i = 0; i < KR; i++) dup |= (L[i] == x);
+        if (!dup) {
+#pragma unroll
+            for (int i = KR - 1; i > 0; i--)
+                L[i] = x < L[i - 1] ? L[i - 1] : (x < L[i] ? x : L[i]);
+            L[0] = x < L[0] ? x : L[0];
         }
     }
 }
 
-template <int NW, bool BIGK, int MODE>
-__global__ __launch_bounds__(64 * NW) void k_search(SearchArgs a)
+// Merges two ascending lists (kNone = empty) into the first k distinct keys.
+// Either list may repeat a key.  Run by one lane.
+__device__ inline void merge_distinct(const uint64_t *a, uint32_t na, const uint64_t *b,
+                                      uint32_t nb, uint32_t k, uint64_t *out)
+{
+    uint32_t i = 0, j = 0, o = 0;
+    uint64_t last = kNone;
+    while (o < k) {
+        const uint64_t x = i < na ? a[i] : kNone;
+        const uint64_t y = j < nb ? b[j] : kNone;
+        const uint64_t m = x < y ? x : y;
+        if (m == kNone) break;
+        if (x == m) i++;
+        if (y == m) j++;
+        if (m != last) {
+            out[o++] = m;
+            last = m;
+        }
+    }
+    for (; o < k; o++) out[o] = kNone;
+}
+
+// Number of keys below the query key in each curve c < C, for the curves
+// c = first + j * step (j < CPW) handled by the calling wave.  Wave-uniform
+// control flow; cnt[j] is the position of curve first + j * step.
+template <int CPW>
+__device__ inline void locate(const IndexView &v, const Key *qk_row, uint32_t first,
+                              uint32_t step, int lane, uint64_t (&cnt)[CPW])
+{
+    const uint32_t C = v.curves;
+    const uint32_t D = v.levels;
+    Key qk[CPW];
+#pragma unroll
+    for (int j = 0; j < CPW; j++) {
+        const uint32_t c = first + j * step;
+        qk[j] = c < C ? qk_row[c] : Key{0, 0};
+    }
+    {   // top table: at most 64 entries
+        Key kk[CPW];
+        const bool valid = (uint64_t)lane < v.len[D];
+#pragma unroll
+        for (int j = 0; j < CPW; j++) {
+            const uint32_t c = first + j * step;
+            kk[j] = (c < C && valid) ? v.lvl[c][D][lane] : Key{~0ull, ~0ull};
+        }
+#pragma unroll
+        for (int j = 0; j < CPW; j++) {
+            const bool less = (first + j * step < C) && valid && key_less(kk[j], qk[j]);
+            cnt[j] = (uint64_t)__popcll(__ballot(less));
+        }
+    }
+    for (int L = (int)D; L >= 1; L--) {
+        // cnt = entries of level L below qkey, so the answer at level L-1 lies in
+        // the 64 entries from 64*(cnt-1) (entry 64*cnt is >= qkey); cnt = 0
+        // means every key is >= qkey.
+        Key kk[CPW];
+        uint64_t base[CPW];
+        const uint64_t len = v.len[L - 1];
+#pragma unroll
+        for (int j = 0; j < CPW; j++) {
+            const uint32_t c = first + j * step;
+            base[j] = cnt[j] ? (cnt[j] - 1) * kFan : 0;
+            const uint64_t idx = base[j] + lane;
+            kk[j] = (c < C && cnt[j] && idx < len) ? v.lvl[c][L - 1][idx] : Key{~0ull, ~0ull};
+        }
+#pragma unroll
+        for (int j = 0; j < CPW; j++) {
+            const uint32_t c = first + j * step;
+            const uint64_t idx = base[j] + lane;
+            const bool less = c < C && cnt[j] && idx < len && key_less(kk[j], qk[j]);
+            const uint64_t m = __ballot(less);
+            cnt[j] = cnt[j] ? base[j] + (uint64_t)__popcll(m) : 0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Search kernel
+// ---------------------------------------------------------------------------
+
+// G: 64-slot groups a wave loads per iteration (rows in flight per lane = 8G).
+// At least 5 waves per SIMD (<= 102 VGPRs) unless the 16-entry list would spill.
+template <int KR, int G, bool BIGK>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((KR > 10 || BIGK) ? 4 : 5)))
+void k_stream(SearchArgs a)
+{
+    __shared__ const uint32_t *s_base[kMaxCurves + 1];   // &ids_c[lo_c]
+    __shared__ uint64_t s_off[kMaxCurves + 1];           // window prefix sums
+    __shared__ uint64_t s_buf[BIGK ? kBuf : 1];
+    __shared__ uint64_t s_run[BIGK ? HC_K_MAX : 1];
+    __shared__ uint64_t s_out[BIGK ? HC_K_MAX : 1];
+
+    const int lane = threadIdx.x;
+    const uint32_t q = blockIdx.x;
+    if (q >= a.nq) return;
+    const uint32_t C = a.v.curves;
+    const uint64_t n = a.v.n;
+    const uint32_t k = a.k;
+
+    // this lane's 16-byte part of the query row
+    const int part = lane & 7;
+    const uint4 qv = *reinterpret_cast<const uint4 *>(a.queries + (uint64_t)q * kDim + 16 * part);
+    const uint32_t qq = __builtin_amdgcn_udot4(qv.x, qv.x, 0u, false) +
+                        __builtin_amdgcn_udot4(qv.y, qv.y, 0u, false) +
+                        __builtin_amdgcn_udot4(qv.z, qv.z, 0u, false) +
+                        __builtin_amdgcn_udot4(qv.w, qv.w, 0u, false);
+    const uint64_t w = a.d_w ? a.d_w[q] : a.w_fixed;
+
+    // ---- 1-2. positions and windows ----------------------------------------
+    uint64_t pos[kMaxCurves];
+    locate<kMaxCurves>(a.v, a.qkeys + (uint64_t)q * C, 0, 1, lane, pos);
+    uint64_t total = 0;
+#pragma unroll
+    for (int c = 0; c < kMaxCurves; c++) {
+        uint64_t lo = 0, cnt = 0;
+        if (c < (int)C) {
+            lo = pos[c] > w ? pos[c] - w : 0;
+            const uint64_t hi = pos[c] + w < n ? pos[c] + w : n;
+            cnt = hi - lo;
+        }
+        if (lane == c) {
+            s_base[c] = c < (int)C ? a.v.ids[c] + lo : nullptr;
+            s_off[c] = total;
+        }
+        total += cnt;
+    }
+    if (lane == kMaxCurves) {
+        s_base[kMaxCurves] = nullptr;
+        s_off[kMaxCurves] = total;
+    }
+    __syncthreads();
+    uint64_t off[kMaxCurves];   // uniform copies of the prefix sums
+#pragma unroll
+    for (int c = 0; c < kMaxCurves; c++) off[c] = s_off[c];
+
+    uint64_t L[KR];
+#pragma unroll
+    for (int i = 0; i < KR; i++) L[i] = kNone;
+    uint32_t nbuf = 0;          // BIGK: keys in s_buf
+    uint64_t tau = kNone;       // BIGK: k-th distinct key so far
+    if constexpr (BIGK) {
+        for (uint32_t i = lane; i < k; i += 64) s_run[i] = kNone;
+    }
+
+    auto flush = [&]() {
+        // sort the buffer, merge it into the running list, tighten tau
+        __syncthreads();
+        for (uint32_t i = nbuf + lane; i < (uint32_t)kBuf; i += 64) s_buf[i] = kNone;
+        __syncthreads();
+        for (uint32_t size = 2; size <= (uint32_t)kBuf; size <<= 1) {
+            for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+                for (uint32_t i = lane; i < (uint32_t)kBuf / 2; i += 64) {
+                    const uint32_t lo = 2 * stride * (i / stride) + (i % stride);
+                    const uint32_t hi = lo + stride;
+                    const bool up = (lo & size) == 0;
+                    const uint64_t x0 = s_buf[lo], x1 = s_buf[hi];
+                    if ((x0 > x1) == up) {
+                        s_buf[lo] = x1;
+                        s_buf[hi] = x0;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if (lane == 0) {
+            merge_distinct(s_run, k, s_buf, nbuf, k, s_out);
+            for (uint32_t i = 0; i < k; i++) s_run[i] = s_out[i];
+        }
+        __syncthreads();
+        tau = s_run[k - 1];
+        nbuf = 0;
+    };
+
+    // ---- 3-5. stream the window slots -------------------------------------
+    for (uint64_t base = 0; base < total; base += 64 * G) {
+        // ids of the G*64 slots: lane l loads slot base + 64 g + l (coalesced)
+        uint32_t myid[G];
+#pragma unroll
+        for (int g = 0; g < G; g++) {
+            const uint64_t s = base + 64 * g + lane;
+            myid[g] = 0;
+            if (s < total) {
+                int c = 0;
+#pragma unroll
+                for (int j = 1; j < kMaxCurves; j++) c += s >= off[j] ? 1 : 0;
+                myid[g] = s_base[c][s - s_off[c]];
+            }
+        }
+        // rows: in step t of group g, lanes 8r..8r+7 read row (g, 8t + r)
+        uint4 x[8 * G];
+#pragma unroll
+        for (int g = 0; g < G; g++)
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                const uint32_t rid = __shfl(myid[g], 8 * t + (lane >> 3), 64);
+                const uint64_t s = base + 64 * g + 8 * t + (lane >> 3);
+                x[8 * g + t] = s < total
+                    ? *reinterpret_cast<const uint4 *>(a.v.db + (uint64_t)rid * kDim + 16 * part)
+                    : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+        for (int g = 0; g < G; g++) {
+            uint32_t mine = 0;
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                uint32_t d = sqdist16(qv, qq, x[8 * g + t]);
+                d += __shfl_xor(d, 1, 64);
+                d += __shfl_xor(d, 2, 64);
+                d += __shfl_xor(d, 4, 64);
+                if (part == t) mine = d;
+            }
+            const uint32_t mid = __shfl(myid[g], 8 * part + (lane >> 3), 64);
+            // this lane now holds slot base + 64 g + 8 part + (lane >> 3)
+            const uint64_t s = base + 64 * g + 8 * part + (lane >> 3);
+            const uint64_t key = s < total ? (((uint64_t)mine << 32) | mid) : kNone;
+            if constexpr (!BIGK) {
+                insert_distinct<KR>(L, key);
+            } else {
+                const bool pass = key < tau;
+                const uint64_t m = __ballot(pass);
+                if (pass) s_buf[nbuf + lanes_below64(m)] = key;
+                nbuf += (uint32_t)__popcll(m);
+                if (nbuf > (uint32_t)(kBuf - 64)) flush();
+            }
+        }
+    }
+
+    if constexpr (!BIGK) {
+        uint64_t mykey = kNone;
+        for (uint32_t j = 0; j < k; j++) {
+            const uint64_t m = wave_min_u64(L[0]);
+            if ((uint32_t)lane == j) mykey = m;
+            if (m != kNone && L[0] == m) {   // every lane holding m pops it
+#pragma unroll
+                for (int i = 0; i < KR - 1; i++) L[i] = L[i + 1];
+                L[KR - 1] = kNone;
+            }
+        }
+        if ((uint32_t)lane < k) {
+            a.out_ids[(uint64_t)q * k + lane] = (uint32_t)mykey;
+            a.out_dists[(uint64_t)q * k + lane] = (uint32_t)(mykey >> 32);
+        }
+    } else {
+        if (nbuf) flush();
+        for (uint32_t i = lane; i < k; i += 64) {
+            const uint64_t key = s_run[i];
+            a.out_ids[(uint64_t)q * k + i] = (uint32_t)key;
+            a.out_dists[(uint64_t)q * k + i] = (uint32_t)(key >> 32);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Set kernel: positions, and the union of the windows built in an LDS hash
+// ---------------------------------------------------------------------------
+
+enum { SET_POS = 0, SET_CAND = 1 };
+
+template <int NW, int MODE>
+__global__ __launch_bounds__(64 * NW) void k_sets(SearchArgs a)
 {
     extern __shared__ uint32_t lds[];
-    constexpr int CPW = (kMaxCurves + NW - 1) / NW;   // curves per wave
+    constexpr int CPW = (kMaxCurves + NW - 1) / NW;
     constexpr int NT = 64 * NW;
     __shared__ uint32_t s_pos[kMaxCurves];
+    __shared__ uint64_t s_wlo[kMaxCurves], s_wn[kMaxCurves];
+    __shared__ const uint32_t *s_ids[kMaxCurves];
     __shared__ uint32_t s_count;
-    constexpr int KCAP = BIGK ? HC_K_MAX : kKR;      // longest running list
-    __shared__ uint64_t s_run[KCAP];
-    __shared__ uint64_t s_tmp[KCAP];
-    __shared__ uint64_t s_out[KCAP];
-    __shared__ uint64_t s_wave[NW][kKR];
 
     const uint32_t cs = 1u << a.cs_log2;
     const uint32_t tsize = 2u * cs;                  // hash slots
     uint32_t *hash = lds;
     uint32_t *list = lds + tsize;
-    uint64_t *ckeys = reinterpret_cast<uint64_t *>(lds);   // overlays hash
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t q = blockIdx.x;
     if (q >= a.nq) return;
     const uint32_t C = a.v.curves;
     const uint64_t n = a.v.n;
-    const uint32_t D = a.v.levels;
 
-    // ---- 1. position of the query key in each curve --------------------
-    {
-        Key qk[CPW];
-        uint64_t cnt[CPW];
+    uint64_t cnt[CPW];
+    locate<CPW>(a.v, a.qkeys + (uint64_t)q * C, wave, NW, lane, cnt);
 #pragma unroll
-        for (int j = 0; j < CPW; j++) {
-            const uint32_t c = wave + j * NW;
-            if (c < C) qk[j] = a.qkeys[(uint64_t)q * C + c];
-            else qk[j] = Key{0, 0};
-        }
-        {   // top table: at most 64 entries
-            Key kk[CPW];
-            const bool valid = (uint64_t)lane < a.v.len[D];
-#pragma unroll
-            for (int j = 0; j < CPW; j++) {
-                const uint32_t c = wave + j * NW;
-                kk[j] = (c < C && valid) ? a.v.lvl[c][D][lane] : Key{~0ull, ~0ull};
-            }
-#pragma unroll
-            for (int j = 0; j < CPW; j++) {
-                const bool less = (wave + j * NW < C) && valid && key_less(kk[j], qk[j]);
-                cnt[j] = (uint64_t)__popcll(__ballot(less));
-            }
-        }
-        for (int L = (int)D; L >= 1; L--) {
-            // cnt = entries of level L below qkey; the answer at level L-1 lies
-            // in the 64 entries starting at 64*(cnt-1) (entry 64*cnt is >= qkey).
-            Key kk[CPW];
-            uint64_t base[CPW];
-            const uint64_t len = a.v.len[L - 1];
-#pragma unroll
-            for (int j = 0; j < CPW; j++) {
-                const uint32_t c = wave + j * NW;
-                base[j] = cnt[j] ? (cnt[j] - 1) * kFan : 0;
-                const uint64_t idx = base[j] + lane;
-                kk[j] = (c < C && cnt[j] && idx < len) ? a.v.lvl[c][L - 1][idx]
-                                                      : Key{~0ull, ~0ull};
-            }
-#pragma unroll
-            for (int j = 0; j < CPW; j++) {
-                const uint32_t c = wave + j * NW;
-                const uint64_t idx = base[j] + lane;
-                const bool less = c < C && cnt[j] && idx < len && key_less(kk[j], qk[j]);
-                const uint64_t m = __ballot(less);
-                cnt[j] = cnt[j] ? base[j] + (uint64_t)__popcll(m) : 0;
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < CPW; j++) {
-            const uint32_t c = wave + j * NW;
-            if (c < C && lane == 0) s_pos[c] = (uint32_t)cnt[j];
-        }
+    for (int j = 0; j < CPW; j++) {
+        const uint32_t c = wave + j * NW;
+        if (c < C && lane == 0) s_pos[c] = (uint32_t)cnt[j];
     }
     __syncthreads();
-    if constexpr (MODE == MODE_POS) {
+    if constexpr (MODE == SET_POS) {
         if (tid < (int)C) a.out_pos[(uint64_t)q * C + tid] = s_pos[tid];
         return;
     }
 
-    // ---- 2. windows ------------------------------------------------------
-    __shared__ uint64_t s_wlo[kMaxCurves], s_wn[kMaxCurves];
-    __shared__ const uint32_t *s_ids[kMaxCurves];
     if (tid < kMaxCurves) {
         const uint64_t w = a.d_w ? a.d_w[q] : a.w_fixed;
         uint64_t lo = 0, hi = 0;
@@ -216,43 +411,38 @@ __global__ __launch_bounds__(64 * NW) void k_search(SearchArgs a)
         s_wn[tid] = hi - lo;
         s_ids[tid] = tid < (int)C ? a.v.ids[tid] : nullptr;
     }
+    if (tid == 0) s_count = 0;
+    for (uint32_t i = tid; i < tsize; i += NT) hash[i] = kEmpty;
     __syncthreads();
     uint64_t total = 0;
 #pragma unroll
     for (int c = 0; c < kMaxCurves; c++) total += s_wn[c];
-    if constexpr (MODE == MODE_CAND) {
-        if (total > cs) {   // the union does not fit one chunk: flag the query
-            if (tid == 0) a.out_counts[q] = 0xFFFFFFFFu;
-            return;
-        }
+    if (total > a.cand_stride) {   // the union might not fit its row: flag the query
+        if (tid == 0) a.out_counts[q] = 0xFFFFFFFFu;
+        return;
     }
-
-    // query bytes for this lane's 16-byte part of a row
-    const int part = lane & 7;
-    const uint4 qv = *reinterpret_cast<const uint4 *>(a.queries + (uint64_t)q * kDim + 16 * part);
-    const uint32_t qq = __builtin_amdgcn_udot4(qv.x, qv.x, 0u, false) +
-                        __builtin_amdgcn_udot4(qv.y, qv.y, 0u, false) +
-                        __builtin_amdgcn_udot4(qv.z, qv.z, 0u, false) +
-                        __builtin_amdgcn_udot4(qv.w, qv.w, 0u, false);
-
-    const uint32_t k = a.k;
-    for (uint32_t i = tid; i < k; i += NT) s_run[i] = kNone;
+    const uint32_t cn = (uint32_t)total;
     const uint32_t hshift = 32u - (a.cs_log2 + 1u);
-
-    for (uint64_t c0 = 0; c0 < total; c0 += cs) {
-        const uint32_t cn = (uint32_t)std::min<uint64_t>(cs, total - c0);
-        // ---- 3. union of the window ids (distinct within the chunk) -----
-        for (uint32_t i = tid; i < tsize; i += NT) hash[i] = kEmpty;
-        if (tid == 0) s_count = 0;
-        __syncthreads();
-        for (uint32_t s = tid; s < cn; s += NT) {
-            uint64_t g = c0 + s;
-            int c = 0;
-            while (g >= s_wn[c]) {
-                g -= s_wn[c];
-                c++;
+    for (uint32_t sb = 0; sb < cn; sb += kIdBatch * NT) {
+        uint32_t idv[kIdBatch];
+#pragma unroll
+        for (int j = 0; j < kIdBatch; j++) {
+            const uint32_t s = sb + tid + j * NT;
+            idv[j] = kEmpty;
+            if (s < cn) {
+                uint64_t g = s;
+                int c = 0;
+                while (g >= s_wn[c]) {
+                    g -= s_wn[c];
+                    c++;
+                }
+                idv[j] = s_ids[c][s_wlo[c] + g];
             }
-            const uint32_t id = s_ids[c][s_wlo[c] + g];
+        }
+#pragma unroll
+        for (int j = 0; j < kIdBatch; j++) {
+            const uint32_t id = idv[j];
+            if (id == kEmpty) continue;
             uint32_t h = (id * 0x9E3779B1u) >> hshift;
             while (true) {
                 const uint32_t prev = atomicCAS(&hash[h], kEmpty, id);
@@ -260,141 +450,26 @@ __global__ __launch_bounds__(64 * NW) void k_search(SearchArgs a)
                 h = (h + 1) & (tsize - 1);
             }
         }
-        __syncthreads();
-        for (uint32_t b = 0; b < tsize; b += NT) {
-            const uint32_t v = hash[b + tid];
-            const bool occ = v != kEmpty;
-            const uint64_t m = __ballot(occ);
-            uint32_t wb = 0;
-            if (lane == 0 && m) wb = atomicAdd(&s_count, (uint32_t)__popcll(m));
-            wb = __shfl(wb, 0, 64);
-            if (occ) list[wb + lanes_below64(m)] = v;
-        }
-        __syncthreads();
-        const uint32_t u = s_count;
-        if constexpr (MODE == MODE_CAND) {
-            if (tid == 0) a.out_counts[q] = u;
-            for (uint32_t i = tid; i < u; i += NT)
-                a.out_cand[(uint64_t)q * a.cand_stride + i] = list[i];
-            return;
-        }
-
-        // ---- 4. distances, 64 rows per wave step --------------------------
-        uint64_t L[kKR];
-#pragma unroll
-        for (int i = 0; i < kKR; i++) L[i] = kNone;
-        for (uint32_t g = wave; g * 64u < u; g += NW) {
-            const uint32_t row0 = g * 64u;
-            uint32_t rid[8];
-            uint4 x[8];
-#pragma unroll
-            for (int s = 0; s < 8; s++) {
-                const uint32_t r = row0 + s * 8 + (lane >> 3);
-                rid[s] = r < u ? list[r] : 0u;
-            }
-#pragma unroll
-            for (int s = 0; s < 8; s++) {
-                const uint32_t r = row0 + s * 8 + (lane >> 3);
-                x[s] = r < u ? *reinterpret_cast<const uint4 *>(a.v.db + (uint64_t)rid[s] * kDim +
-                                                                16 * part)
-                             : make_uint4(0, 0, 0, 0);
-            }
-            uint32_t mine = 0, myid = 0;
-#pragma unroll
-            for (int s = 0; s < 8; s++) {
-                uint32_t d = sqdist16(qv, qq, x[s]);
-                d += __shfl_xor(d, 1, 64);
-                d += __shfl_xor(d, 2, 64);
-                d += __shfl_xor(d, 4, 64);
-                if (part == s) {
-                    mine = d;
-                    myid = rid[s];
-                }
-            }
-            const uint32_t myrow = row0 + part * 8 + (lane >> 3);
-            const uint64_t key = myrow < u ? (((uint64_t)mine << 32) | myid) : kNone;
-            if constexpr (BIGK) {
-                if (myrow < u) ckeys[myrow] = key;
-            } else {
-                list_insert(L, key);
-            }
-        }
-
-        // ---- 5. k nearest of the chunk, merged into the running list ------
-        if constexpr (!BIGK) {
-            uint64_t mykey = kNone;
-            for (uint32_t j = 0; j < k; j++) {
-                const uint64_t m = wave_min_u64(L[0]);
-                if ((uint32_t)lane == j) mykey = m;
-                if (m != kNone && L[0] == m) {
-#pragma unroll
-                    for (int i = 0; i < kKR - 1; i++) L[i] = L[i + 1];
-                    L[kKR - 1] = kNone;
-                }
-            }
-            if (NW == 1 && c0 == 0 && cn == total) {
-                // the whole union fit in one chunk: write the result directly
-                if ((uint32_t)lane < k) {
-                    a.out_ids[(uint64_t)q * k + lane] = (uint32_t)mykey;
-                    a.out_dists[(uint64_t)q * k + lane] = (uint32_t)(mykey >> 32);
-                }
-                return;
-            }
-            if ((uint32_t)lane < k) s_wave[wave][lane] = mykey;
-            __syncthreads();
-            if (tid == 0) {
-                for (int wv = 0; wv < NW; wv++) {
-                    merge_distinct(s_run, s_wave[wv], k, s_out);
-                    for (uint32_t i = 0; i < k; i++) s_run[i] = s_out[i];
-                }
-            }
-            __syncthreads();
-        } else {
-            __syncthreads();
-            uint32_t p2 = 1;
-            while (p2 < u) p2 <<= 1;
-            for (uint32_t i = u + tid; i < p2; i += NT) ckeys[i] = kNone;
-            __syncthreads();
-            for (uint32_t size = 2; size <= p2; size <<= 1) {
-                for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-                    for (uint32_t i = tid; i < p2 / 2; i += NT) {
-                        const uint32_t lo = 2 * stride * (i / stride) + (i % stride);
-                        const uint32_t hi = lo + stride;
-                        const bool up = (lo & size) == 0;
-                        const uint64_t x0 = ckeys[lo], x1 = ckeys[hi];
-                        if ((x0 > x1) == up) {
-                            ckeys[lo] = x1;
-                            ckeys[hi] = x0;
-                        }
-                    }
-                    __syncthreads();
-                }
-            }
-            for (uint32_t i = tid; i < k; i += NT) s_tmp[i] = i < u ? ckeys[i] : kNone;
-            __syncthreads();
-            if (tid == 0) {
-                merge_distinct(s_run, s_tmp, k, s_out);
-                for (uint32_t i = 0; i < k; i++) s_run[i] = s_out[i];
-            }
-            __syncthreads();
-        }
     }
-    if constexpr (MODE == MODE_CAND) {
-        // empty union: no chunk ran
-        if (tid == 0) a.out_counts[q] = 0;
-        return;
+    __syncthreads();
+    for (uint32_t b = 0; b < tsize; b += NT) {
+        const uint32_t v = hash[b + tid];
+        const bool occ = v != kEmpty;
+        const uint64_t m = __ballot(occ);
+        uint32_t wb = 0;
+        if (lane == 0 && m) wb = atomicAdd(&s_count, (uint32_t)__popcll(m));
+        wb = __shfl(wb, 0, 64);
+        if (occ) list[wb + lanes_below64(m)] = v;
     }
-    for (uint32_t i = tid; i < k; i += NT) {
-        const uint64_t key = s_run[i];
-        a.out_ids[(uint64_t)q * k + i] = (uint32_t)key;
-        a.out_dists[(uint64_t)q * k + i] = (uint32_t)(key >> 32);
-    }
+    __syncthreads();
+    const uint32_t u = s_count;
+    if (tid == 0) a.out_counts[q] = u;
+    for (uint32_t i = tid; i < u; i += NT) a.out_cand[(uint64_t)q * a.cand_stride + i] = list[i];
 }
 
-struct LaunchShape {
-    int nw;
-    uint32_t cs_log2;
-};
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
 
 static uint32_t ceil_log2(uint64_t x)
 {
@@ -403,31 +478,39 @@ static uint32_t ceil_log2(uint64_t x)
     return l;
 }
 
-// Chunk capacity and waves per query from the (typical) window w.
-static LaunchShape pick_shape(uint64_t w_hint, uint32_t max_slots)
+template <int KR, int G, bool BIGK>
+static hc_status launch_stream(const SearchArgs &a, hipStream_t st)
 {
-    const uint64_t slots = std::max<uint64_t>(16 * std::max<uint64_t>(w_hint, 1), 64);
-    LaunchShape s;
-    s.nw = slots > 1024 ? 4 : 1;
-    uint64_t cs = std::min<uint64_t>(slots, max_slots);
-    cs = std::max<uint64_t>(cs, 64u * s.nw);
-    s.cs_log2 = ceil_log2(cs);
-    return s;
-}
-
-template <int NW, bool BIGK, int MODE>
-static hc_status launch(const SearchArgs &a, hipStream_t st)
-{
-    const size_t lds = (size_t)12 << a.cs_log2;
-    hipLaunchKernelGGL((k_search<NW, BIGK, MODE>), dim3(a.nq), dim3(64 * NW), lds, st, a);
+    hipLaunchKernelGGL((k_stream<KR, G, BIGK>), dim3(a.nq), dim3(64), 0, st, a);
     return last_hip();
 }
 
-template <int MODE>
-static hc_status launch_mode(const SearchArgs &a, int nw, bool bigk, hipStream_t st)
+// A register list as long as k (1, 4, 10 or 16) for k <= 16, the LDS buffer
+// beyond.
+template <int G>
+static hc_status launch_search_g(const SearchArgs &a, hipStream_t st)
 {
-    if (nw == 1) return bigk ? launch<1, true, MODE>(a, st) : launch<1, false, MODE>(a, st);
-    return bigk ? launch<4, true, MODE>(a, st) : launch<4, false, MODE>(a, st);
+    if (a.k == 1) return launch_stream<1, G, false>(a, st);
+    if (a.k <= 4) return launch_stream<4, G, false>(a, st);
+    if (a.k <= 10) return launch_stream<10, G, false>(a, st);
+    if (a.k <= (uint32_t)kKR) return launch_stream<kKR, G, false>(a, st);
+    return launch_stream<1, G, true>(a, st);
+}
+
+static hc_status launch_search(const SearchArgs &a, uint64_t w_hint, hipStream_t st)
+{
+    // Measured on MI355X at 10^7 rows: one group with at least 5 waves per SIMD
+    // is within 1% of two groups for w >= 256 and faster below.
+    (void)w_hint;
+    return launch_search_g<1>(a, st);
+}
+
+template <int NW, int MODE>
+static hc_status launch_sets(const SearchArgs &a, hipStream_t st)
+{
+    const size_t lds = MODE == SET_CAND ? (size_t)12 << a.cs_log2 : 0;
+    hipLaunchKernelGGL((k_sets<NW, MODE>), dim3(a.nq), dim3(64 * NW), lds, st, a);
+    return last_hip();
 }
 
 static hc_status check_common(const hc_index *idx, const uint8_t *d_queries, void *d_scratch,
@@ -489,9 +572,7 @@ hc_status hc_search_encoded(const hc_index *idx, const uint8_t *d_queries, uint3
     a.out_ids = d_out_ids;
     a.out_dists = d_out_dists;
     const uint64_t hint = d_w ? (w_fixed ? w_fixed : 64) : w_fixed;
-    LaunchShape sh = pick_shape(hint, kMaxChunk);
-    a.cs_log2 = sh.cs_log2;
-    return launch_mode<MODE_SEARCH>(a, sh.nw, k > (uint32_t)kKR, (hipStream_t)stream);
+    return launch_search(a, hint, (hipStream_t)stream);
 }
 
 hc_status hc_search_batch(const hc_index *idx, const uint8_t *d_queries, uint32_t nq,
@@ -519,8 +600,7 @@ hc_status hc_positions(const hc_index *idx, const uint8_t *d_queries, uint32_t n
     st = encode_rows(a.v, d_queries, nq, (Key *)d_scratch, s);
     if (st != HC_OK) return st;
     a.out_pos = d_pos;
-    a.cs_log2 = 6;
-    return launch_mode<MODE_POS>(a, 1, false, s);
+    return launch_sets<1, SET_POS>(a, s);
 }
 
 hc_status hc_candidates(const hc_index *idx, const uint8_t *d_queries, uint32_t nq,
@@ -532,20 +612,21 @@ hc_status hc_candidates(const hc_index *idx, const uint8_t *d_queries, uint32_t 
     if (nq == 0) return HC_OK;
     hc_status st = check_common(idx, d_queries, d_scratch, scratch_bytes, nq);
     if (st != HC_OK) return st;
-    if (stride > kMaxChunk) return HC_ERR_UNSUPPORTED;
+    if (stride > kMaxSetSlots) return HC_ERR_UNSUPPORTED;
     if (!d_w && (uint64_t)stride < 16ull * w_fixed) return HC_ERR_SIZE;
     hipStream_t s = (hipStream_t)stream;
     SearchArgs a = base_args(idx, d_queries, nq, d_scratch);
     st = encode_rows(a.v, d_queries, nq, (Key *)d_scratch, s);
     if (st != HC_OK) return st;
-    a.w_fixed = d_w ? std::min<uint32_t>(w_fixed, stride / 16) : w_fixed;
+    a.w_fixed = w_fixed;
     a.d_w = d_w;
     a.out_counts = d_counts;
     a.out_cand = d_ids;
     a.cand_stride = stride;
-    // one chunk must hold the whole union: capacity >= stride >= 16 w
+    // the union must fit one table: capacity >= stride >= 16 w
     a.cs_log2 = std::max<uint32_t>(ceil_log2(std::max<uint32_t>(stride, 64)), 6);
-    return launch_mode<MODE_CAND>(a, 1, false, s);
+    if ((1u << a.cs_log2) > 1024) return launch_sets<4, SET_CAND>(a, s);
+    return launch_sets<1, SET_CAND>(a, s);
 }
 
 }  // extern "C"
