@@ -1,12 +1,22 @@
 """Benchmark of the batched Multicurves search on one MI355X.
 
-One step = one pass of the search path (query keys, binary search, windows,
-union, distances, top-k) over a batch of Q queries resident in HBM, through
-the C ABI (hc_search_batch = hc_encode_queries + hc_search_encoded).
+Workload: N = 10,000,000 mixture vectors (128 x uint8, 1.28 GB) indexed by 8
+curves of 16 dims; a batch of Q = 100,000 queries resident in HBM; k = 10.
 
-Workload (default): N = 10,000,000 mixture vectors (128 x uint8, 1.28 GB),
-8 curves of 16 dims, Q = 100,000 queries, k = 10, w in {16, 64, 256}.
-Prints one JSON line (see the keys below).
+One step = one pass of the search path over the batch, through the C ABI:
+  fixed w:   hc_encode_queries + hc_search_encoded
+  learned w: hc_features (which also encodes the query keys) + hc_mlp_infer +
+             hc_search_encoded with the per-query w.
+The metric is queries/s at mean recall@10 >= 0.90 (exact kNN truth for the
+first --recall-q queries).  Both the fixed w and the learned model's offset
+delta are calibrated to that recall on separate calibration queries (seed 5);
+the learned model is trained on the GPU on --train queries (seed 3) with
+labels from exact kNN.  Also measured: the windows w in --sweep (w = 16, 64,
+256 are the plain-method points), each with its recall and the search
+kernel's algorithmic HBM bytes / time; p50/p99 of 1,000-query sub-batches;
+and the CPU oracle on a bounded sample.
+
+Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
 import json
@@ -20,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TARGET = 0.90
 
 
 def log(msg):
@@ -29,25 +40,22 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=10_000_000)
     ap.add_argument("--nq", type=int, default=100_000)
     ap.add_argument("--k", type=int, default=10)
-    ap.add_argument("--w", type=int, default=64, help="w of the headline line")
-    ap.add_argument("--sweep", default="16,64,256", help="w values measured")
+    ap.add_argument("--sweep", default="16,64,256,1024,4096")
+    ap.add_argument("--sweep-steps", type=int, default=3)
     ap.add_argument("--recall-q", type=int, default=1000)
+    ap.add_argument("--calib-q", type=int, default=10_000)
+    ap.add_argument("--train", type=int, default=200_000, help="0 = no learned w")
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--w-max", type=int, default=1 << 17)
     ap.add_argument("--latency-batch", type=int, default=1000)
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="queries of the oracle sample (0 = sized to ~15 s)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
-
-
-def recall_at(ids, truth):
-    k = truth.shape[1]
-    hits = [len(set(a.tolist()) & set(b.tolist())) for a, b in zip(ids, truth)]
-    return float(np.mean(hits)) / k
 
 
 def main():
@@ -57,10 +65,11 @@ def main():
               "(the multi-GPU design is described, not built)", flush=True)
         sys.exit(2)
     import torch
-    from paper_1209_0410_amd import datagen
+    from paper_1209_0410_amd import datagen, learned
     from paper_1209_0410_amd.index import Index, brute_force
 
     dev = torch.device("cuda:0")
+    k = a.k
     t0 = time.time()
     db = datagen.make_db(a.n)
     q = datagen.make_queries(a.nq)
@@ -72,89 +81,121 @@ def main():
     ix = Index(gdb)
     torch.cuda.synchronize()
     build_s = time.time() - t0
+    rank = learned.ranks(ix)
     log(f"index build {build_s:.3f}s ({ix.index_bytes / 1e9:.2f} GB)")
 
-    k = a.k
     stream = torch.cuda.current_stream()
     sc = ix.scratch(a.nq)
     out = (torch.empty((a.nq, k), dtype=torch.int32, device=dev),
            torch.empty((a.nq, k), dtype=torch.int32, device=dev))
 
-    # recall truth: exact kNN on the GPU for the first recall-q queries
+    # exact kNN truth for the first recall-q queries of the batch
     rq = min(a.recall_q, a.nq)
     tid, _ = brute_force(gdb, gq[:rq].contiguous(), k)
     truth = tid.cpu().numpy().view(np.uint32)
-    log(f"brute-force truth for {rq} queries")
+    cross = check_truth(db, q, truth, k) if a.cpu_baseline else None
+    log(f"truth for {rq} queries" + ("" if cross is None else f"; oracle agrees on {cross}"))
 
-    sweep = sorted({int(x) for x in a.sweep.split(",") if x} | {a.w})
-    rows = {}
-    for w in sweep:
-        for _ in range(a.warmup):
-            ix.search(gq, k, w, out=out, scratch=sc)
+    def recall_of(ids_t):
+        return learned.recall_at_k(ids_t[:rq].cpu().numpy().view(np.uint32), truth)
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
         torch.cuda.synchronize()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
-               torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
-        torch.cuda.synchronize()
+        marks = []
         t_wall = time.perf_counter()
-        for e0, e1, e2 in ev:
-            e0.record(stream)
-            ix.encode_queries(gq, sc)
-            e1.record(stream)
-            ix.search_encoded(gq, k, w, out, sc)
-            e2.record(stream)
+        for _ in range(steps):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            fn(ev, stream)
+            marks.append(ev)
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t_wall
-        step_ms = [e0.elapsed_time(e2) for e0, _, e2 in ev]
-        kern_ms = [e1.elapsed_time(e2) for _, e1, e2 in ev]
-        enc_ms = [e0.elapsed_time(e1) for e0, e1, _ in ev]
-        ids = out[0][:rq].cpu().numpy().view(np.uint32)
-        rec = recall_at(ids, truth)
-        # algorithmic bytes of the search kernel: window ids, distinct rows, results
-        wsum = 0
-        ucount = None
-        if 16 * w <= 4096:
-            counts, _ = ix.candidates(gq, w)
-            ucount = counts.cpu().numpy().view(np.uint32).astype(np.int64)
-        pos = ix.positions(gq).cpu().numpy().view(np.uint32).astype(np.int64)
-        lo = np.maximum(pos - w, 0)
-        hi = np.minimum(pos + w, a.n)
-        wsum = int((hi - lo).sum())
-        rows[w] = dict(w=w, step_ms=float(np.median(step_ms)), kernel_ms=float(np.mean(kern_ms)),
-                       kernel_ms_median=float(np.median(kern_ms)),
-                       encode_ms=float(np.mean(enc_ms)), wall_ms=wall * 1e3 / a.steps,
-                       recall=rec, window_ids=wsum,
-                       unique=None if ucount is None else int(ucount.sum()))
-        r = rows[w]
-        if r["unique"] is not None:
-            alg = 4 * wsum + 128 * r["unique"] + 8 * k * a.nq
-            r["alg_bytes"] = alg
-            r["alg_GBs"] = alg / (r["kernel_ms"] * 1e-3) / 1e9
-        log(f"w={w} step {r['step_ms']:.3f} ms kernel {r['kernel_ms']:.3f} ms "
-            f"q/s {a.nq / r['step_ms'] * 1e3:.3e} recall@{k} {rec:.4f} "
-            f"U/q {None if r['unique'] is None else r['unique'] / a.nq:.1f} "
-            f"GB/s {r.get('alg_GBs', 0):.0f}")
+        wall = (time.perf_counter() - t_wall) / steps
+        step = [e[0].elapsed_time(e[2]) for e in marks]
+        kern = [e[1].elapsed_time(e[2]) for e in marks]
+        return float(np.median(step)), float(np.mean(kern)), wall * 1e3
 
-    head = rows[a.w]
-    # batch latency: sub-batches timed one by one
+    def fixed_step(w):
+        def fn(ev=None, st=None):
+            if ev: ev[0].record(st)
+            ix.encode_queries(gq, sc)
+            if ev: ev[1].record(st)
+            ix.search_encoded(gq, k, w, out, sc)
+            if ev: ev[2].record(st)
+        return fn
+
+    def alg_bytes(wsum_slots, union):
+        # window ids read + distinct rows gathered + results written
+        return 4 * wsum_slots + 128 * union + 8 * k * a.nq
+
+    def window_slots(w_arr):
+        pos = ix.positions(gq).cpu().numpy().view(np.uint32).astype(np.int64)
+        w_arr = np.broadcast_to(np.asarray(w_arr, np.int64).reshape(-1, 1), pos.shape)
+        return int((np.minimum(pos + w_arr, a.n) - np.maximum(pos - w_arr, 0)).sum())
+
+    # ---- fixed-w sweep ---------------------------------------------------------
+    rows = []
+    for w in sorted({int(x) for x in a.sweep.split(",") if x}):
+        step_ms, kern_ms, wall_ms = timed(fixed_step(w), a.sweep_steps, 1)
+        rec = recall_of(out[0])
+        uni = int(learned.union_sizes(ix, rank, gq, w).cpu().numpy().view(np.uint32).sum())
+        slots = window_slots(w)
+        ab = alg_bytes(slots, uni)
+        rows.append(dict(w=w, step_ms=step_ms, kernel_ms=kern_ms, qps=a.nq / step_ms * 1e3,
+                         recall=rec, union_per_query=uni / a.nq, alg_bytes=ab,
+                         alg_GBs=ab / (kern_ms * 1e-3) / 1e9,
+                         frac=ab / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS))
+        r = rows[-1]
+        log(f"fixed w={w}: {step_ms:.3f} ms/step, {r['qps']:.3e} q/s, recall {rec:.4f}, "
+            f"union/q {r['union_per_query']:.0f}, {r['alg_GBs']:.0f} GB/s ({r['frac']:.1%})")
+
+    # ---- calibration at recall >= 0.90 ------------------------------------------
+    cq = datagen.make_queries(a.calib_q, seed=datagen.SEED_CALIB)
+    gcq = torch.from_numpy(cq).to(dev)
+    ctruth, _ = brute_force(gdb, gcq, k)
+    w_fix, rec_c = learned.calibrate_fixed_w(ix, gcq, ctruth, k, TARGET, hi=a.w_max)
+    log(f"calibrated fixed w = {w_fix} (calibration recall {rec_c:.4f})")
+    fs, fk, fwall = timed(fixed_step(w_fix), a.steps, a.warmup)
+    f_rec = recall_of(out[0])
+    f_uni = int(learned.union_sizes(ix, rank, gq, w_fix).cpu().numpy().view(np.uint32).sum())
+    f_ab = alg_bytes(window_slots(w_fix), f_uni)
+    fixed = dict(w=w_fix, step_ms=fs, kernel_ms=fk, wall_ms=fwall, qps=a.nq / fs * 1e3,
+                 recall=f_rec, union_per_query=f_uni / a.nq, alg_bytes=f_ab,
+                 alg_GBs=f_ab / (fk * 1e-3) / 1e9)
+    log(f"fixed w={w_fix}: {fs:.3f} ms/step, {fixed['qps']:.3e} q/s, recall {f_rec:.4f}")
+
+    learned_row = None
+    if a.train > 0:
+        learned_row = run_learned(a, ix, rank, gdb, gq, gcq, ctruth, out, sc, timed, recall_of,
+                                  alg_bytes, window_slots, dev)
+
+    head = learned_row if learned_row is not None else fixed
+
+    # ---- batch latency of the headline method ------------------------------------
     lb = min(a.latency_batch, a.nq)
     lat = []
     for i in range(0, a.nq - lb + 1, lb):
         sub = gq[i:i + lb]
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        ix.search(sub, k, a.w, out=(out[0][i:i + lb], out[1][i:i + lb]), scratch=sc)
+        if learned_row is not None:
+            learned.search_learned(ix, head["_model"], sub, k,
+                                   (out[0][i:i + lb], out[1][i:i + lb]), sc)
+        else:
+            ix.search(sub, k, w_fix, out=(out[0][i:i + lb], out[1][i:i + lb]), scratch=sc)
         e1.record(stream)
         lat.append((e0, e1))
     torch.cuda.synchronize()
     lat_ms = np.array([e0.elapsed_time(e1) for e0, e1 in lat])
+    head.pop("_model", None)
 
     cpu = None
     if a.cpu_baseline:
-        cpu = cpu_baseline(db, q, k, a.w, a.cpu_sample)
+        cpu = cpu_baseline(db, q, k, w_fix, a.cpu_seconds)
 
     result = {
         "metric": "queries/s at recall@10≥0.90, learned-w vs fixed-w, 1 GPU; p50/p99 latency",
-        "value": a.nq / (head["step_ms"] * 1e-3),
+        "value": head["qps"],
         "unit": "queries/s",
         "n_gpus": 1,
         "steps": a.steps,
@@ -165,48 +206,130 @@ def main():
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": f"plain method on GPU: N={a.n} mixture uint8 d=128, 8 curves x 16 "
-                               f"dims, Q={a.nq}, k={k}, fixed w={a.w}",
-                   "n": a.n, "nq": a.nq, "k": k, "w": a.w, "curves": 8},
+        "config": {"workload": f"Multicurves search on one GPU: N={a.n} mixture uint8 d=128, "
+                               f"8 curves x 16 dims, Q={a.nq} per batch, k={k}, "
+                               f"{'learned' if learned_row else 'fixed'} w at recall@10>=0.90",
+                   "n": a.n, "nq": a.nq, "k": k, "curves": 8,
+                   "method": "learned-w" if learned_row else "fixed-w"},
         "recall_at_10": head["recall"],
-        "recall_target_met": bool(head["recall"] >= 0.90),
         "recall_queries": rq,
+        "fixed_w": fixed,
+        "learned_w": learned_row,
+        "learned_vs_fixed_qps": (learned_row["qps"] / fixed["qps"]) if learned_row else None,
         "latency_ms": {"batch": lb, "p50": float(np.percentile(lat_ms, 50)),
                        "p99": float(np.percentile(lat_ms, 99))},
         "build_s": build_s,
-        "sweep": [{kk: v for kk, v in r.items()} for r in rows.values()],
+        "sweep": rows,
+        "roofline": {"bound": "hbm", "achieved": head["alg_GBs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": head["alg_GBs"] / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_stream (hc_search_encoded)",
+                     "kernel_ms": head["kernel_ms"],
+                     "alg_bytes_per_launch": head["alg_bytes"]},
     }
-    if head.get("alg_GBs") is not None:
-        result["roofline"] = {"bound": "hbm", "achieved": head["alg_GBs"], "peak": HBM_PEAK_GBS,
-                              "unit": "GB/s", "frac": head["alg_GBs"] / HBM_PEAK_GBS,
-                              "traffic": None, "kernel": "k_search",
-                              "kernel_ms": head["kernel_ms"],
-                              "alg_bytes_per_launch": head["alg_bytes"]}
     if cpu is not None:
         result["cpu_baseline"] = cpu
     print(json.dumps(result), flush=True)
 
 
-def cpu_baseline(db, q, k, w, sample):
-    """The oracle's search, timed on the host cores on a bounded query sample."""
+def run_learned(a, ix, rank, gdb, gq, gcq, ctruth, out, sc, timed, recall_of, alg_bytes,
+                window_slots, dev):
+    import torch
+    from paper_1209_0410_amd import datagen, learned
+    from paper_1209_0410_amd.index import brute_force
+    k = a.k
+    t0 = time.time()
+    tq = datagen.make_queries(a.train, seed=datagen.SEED_TRAIN)
+    gtq = torch.from_numpy(tq).to(dev)
+    ttruth, _ = brute_force(gdb, gtq, k)
+    lab = learned.labels(ix, rank, gtq, ttruth)
+    feats = learned.features(ix, gtq, k)
+    torch.cuda.synchronize()
+    labs = lab.cpu().numpy().view(np.uint32)
+    log(f"labels for {a.train} training queries in {time.time() - t0:.1f}s; "
+        f"w* p10/50/90 = {np.percentile(labs, [10, 50, 90]).tolist()}")
+    model = learned.WModel(dev, seed=0, w_min=8, w_max=a.w_max)
+    model.set_norm(feats)
+    y = model.targets(lab)
+    t0 = time.time()
+    losses = model.train(feats, y, epochs=a.epochs, batch=4096, lr=1e-3, seed=1)
+    torch.cuda.synchronize()
+    train_s = time.time() - t0
+    log(f"trained {a.epochs} epochs in {train_s:.1f}s, loss {losses[0]:.3f} -> {losses[-1]:.3f}")
+    cfeats = learned.features(ix, gcq, k)
+    delta, rec_c = learned.calibrate_delta(ix, model, gcq, cfeats, ctruth, k, TARGET)
+    model.delta = delta
+    log(f"calibrated delta = {delta:.3f} (calibration recall {rec_c:.4f})")
+    feats_b = torch.empty((a.nq, learned.FEATURES), dtype=torch.float32, device=dev)
+    wq = torch.empty(a.nq, dtype=torch.int32, device=dev)
+
+    def fn(ev=None, st=None):
+        if ev is None:
+            learned.search_learned(ix, model, gq, k, out, sc, feats=feats_b, w=wq)
+            return
+        ev[0].record(st)
+        _learned_split(ix, model, gq, k, out, sc, feats_b, wq, ev, st)
+        ev[2].record(st)
+
+    ls, lk, lwall = timed(fn, a.steps, a.warmup)
+    rec = recall_of(out[0])
+    wv = wq.cpu().numpy().view(np.uint32)
+    uni = int(learned.union_sizes(ix, rank, gq, 0, wq).cpu().numpy().view(np.uint32).sum())
+    ab = alg_bytes(window_slots(wv.astype(np.int64)), uni)
+    row = dict(step_ms=ls, kernel_ms=lk, wall_ms=lwall, qps=a.nq / ls * 1e3, recall=rec,
+               delta=delta, mean_w=float(wv.mean()),
+               w_pct=np.percentile(wv, [10, 50, 90, 99]).tolist(),
+               union_per_query=uni / a.nq, alg_bytes=ab, alg_GBs=ab / (lk * 1e-3) / 1e9,
+               train_queries=a.train, epochs=a.epochs, loss=[losses[0], losses[-1]],
+               train_s=train_s)
+    log(f"learned: {ls:.3f} ms/step, {row['qps']:.3e} q/s, recall {rec:.4f}, mean w "
+        f"{row['mean_w']:.0f}")
+    row["_model"] = model
+    return row
+
+
+def _learned_split(ix, model, gq, k, out, sc, feats_b, wq, ev, st):
+    """The learned step with an event between the MLP and the search kernel."""
+    from paper_1209_0410_amd import capi, learned
+    from paper_1209_0410_amd.index import _ptr, _stream
+    nq = gq.shape[0]
+    capi.call("hc_features", ix.handle, _ptr(gq), nq, int(k), None, _ptr(feats_b), _ptr(sc),
+              sc.numel(), _stream())
+    capi.call("hc_mlp_infer", _ptr(model.bf16), _ptr(model.norm), _ptr(feats_b), nq,
+              float(model.delta), model.w_min, model.w_max, 64, _ptr(wq), None, _stream())
+    ev[1].record(st)
+    ix.search_encoded(gq, k, 0, out, sc, w_per_query=wq)
+
+
+def check_truth(db, q, truth, k, m=16):
+    """The GPU exact kNN against the oracle's on the first m queries."""
+    import oracle
+    ids, _ = oracle.brute_force(db, q[:m], k)
+    if not (ids == truth[:m]).all():
+        raise AssertionError("GPU brute force differs from the oracle")
+    return f"{m} queries"
+
+
+def cpu_baseline(db, q, k, w, seconds):
+    """The oracle's search timed on the host cores on a bounded query sample."""
     import oracle
     t0 = time.time()
     oix = oracle.Index(db)
     build = time.time() - t0
     log(f"oracle index build {build:.1f}s")
-    if sample <= 0:
-        t0 = time.time()
-        oix.search(q[:200], k, w)
-        per = (time.time() - t0) / 200
-        sample = int(min(len(q), max(200, 15.0 / max(per, 1e-9))))
+    t0 = time.time()
+    probe = 32
+    oix.search(q[:probe], k, w)
+    per = (time.time() - t0) / probe
+    sample = int(min(len(q), max(probe, seconds / max(per, 1e-9))))
     t0 = time.time()
     oix.search(q[:sample], k, w)
     dt = time.time() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     log(f"oracle search {sample} queries in {dt:.1f}s on {threads} threads")
     return {"value": sample / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {sample} of the batch's queries, same index shape and w={w}, "
-                      f"k={k}; oracle index built separately in {build:.1f}s"}
+            "sample": f"first {sample} queries of the batch at the calibrated fixed w={w}, "
+                      f"k={k}, same N; the oracle's own index, built in {build:.1f}s "
+                      f"(not timed)"}
 
 
 if __name__ == "__main__":

@@ -186,6 +186,87 @@ hc_status hc_brute_force(const uint8_t *d_db, uint64_t n, const uint8_t *d_queri
                          uint32_t *d_out_dists, void *d_scratch, size_t scratch_bytes,
                          hc_stream stream);
 
+/* ---------------------------------------------------------------------- */
+/* Learned probe depth                                                     */
+/*                                                                        */
+/* The paper's probe depth is one value for every query.  These entry     */
+/* points predict a window w per query with a small MLP over cheap        */
+/* features of the query's neighbourhood in the curves, and produce the   */
+/* labels it is trained on.  Search stays exact given the w array.        */
+/* ---------------------------------------------------------------------- */
+
+#define HC_FEATURES 24u
+#define HC_MLP_PARAMS 5825u   /* 24 -> 64 -> 64 -> 1 */
+
+/* Place of every id in every list: d_rank[id * curves + c] = r such that curve
+ * c's list holds id at r (n * curves uint32). */
+hc_status hc_index_ranks(const hc_index *idx, uint32_t *d_rank, hc_stream stream);
+
+/* Label of each query: the smallest w whose candidate union holds all of its
+ * exact top-k (d_truth_ids, nq x k, from hc_brute_force; 0xFFFFFFFF = none).
+ * Curve c's window of w holds id j iff r_c(j) <= w, with r_c(j) =
+ * pos_c - rank_c(j) when rank_c(j) < pos_c and rank_c(j) - pos_c + 1
+ * otherwise; so label = max over j of min over c of r_c(j).  A search with w
+ * >= label returns exactly the truth (the union then contains it, and the
+ * top-k of a superset of it is itself). */
+hc_status hc_labels(const hc_index *idx, const uint32_t *d_rank, const uint8_t *d_queries,
+                    uint32_t nq, uint32_t k, const uint32_t *d_truth_ids, uint32_t *d_labels,
+                    void *d_scratch, size_t scratch_bytes, hc_stream stream);
+
+/* Size of every query's candidate set (the union of Alg. 2) for any w: a
+ * window slot of curve c counts unless its id lies in the window of a curve
+ * c' < c.  w as in hc_search_batch. */
+hc_status hc_union_sizes(const hc_index *idx, const uint32_t *d_rank, const uint8_t *d_queries,
+                         uint32_t nq, uint32_t w_fixed, const uint32_t *d_w, uint32_t *d_counts,
+                         void *d_scratch, size_t scratch_bytes, hc_stream stream);
+
+/* HC_FEATURES floats per query (d_feat, nq x 24), FP32; every list place is
+ * clamped to [0, n-1]:
+ *  [0..5]   min over curves of log2(1 + |key_c[pos_c + o'] - qkey_c|) for
+ *           o = -64, -8, -1, +1, +8, +64 (o' = o if o < 0, else o - 1)
+ *  [6..11]  the mean over curves of the same
+ *  [12..19] log2(1 + squared distance to the entry at pos_c), curve c
+ *  [20]     log2(k) (d_k[q] if d_k != NULL, else k)
+ *  [21..23] max over curves of log2(1 + key_c[pos_c + s - 1] - key_c[pos_c - s])
+ *           for s = 1, 8, 64. */
+hc_status hc_features(const hc_index *idx, const uint8_t *d_queries, uint32_t nq, uint32_t k,
+                      const uint32_t *d_k, float *d_feat, void *d_scratch, size_t scratch_bytes,
+                      hc_stream stream);
+
+/* MLP inference.  Parameters (BF16, HC_MLP_PARAMS): W1[64][24], b1[64],
+ * W2[64][64], b2[64], W3[64], b3; ReLU after both hidden layers; FP32
+ * arithmetic.  Inputs are standardised as (f - mean) / std with d_norm =
+ * {mean[24], std[24]} (NULL = raw).  y = MLP(x) estimates log2 of the label;
+ * w = clamp(ceil(2^(y + delta)), w_min, w_max), or w_fallback when a
+ * standardised feature or y + delta is not finite (y is then NaN).  d_w_out (nq uint32) and/or d_y_out (nq float) may be NULL. */
+hc_status hc_mlp_infer(const uint16_t *d_params_bf16, const float *d_norm, const float *d_feat,
+                       uint32_t nq, float delta, uint32_t w_min, uint32_t w_max,
+                       uint32_t w_fallback, uint32_t *d_w_out, float *d_y_out, hc_stream stream);
+
+/* Training.  A batch is rows d_idx[0..batch) of d_x (NULL = rows 0..batch-1),
+ * standardised with d_norm.  hc_mlp_forward writes y (batch floats).
+ * hc_mlp_backward computes the gradient of loss = mean over the batch of
+ * (y - d_target[row])^2 into d_grad (HC_MLP_PARAMS floats, layout of the
+ * parameters) and the loss into *d_loss (device, may be NULL); the sums over
+ * the batch run in sample order, so the result is deterministic. */
+hc_status hc_mlp_train_scratch_bytes(uint32_t batch, size_t *bytes);
+hc_status hc_mlp_forward(const uint16_t *d_params_bf16, const float *d_norm, const float *d_x,
+                         const uint32_t *d_idx, uint32_t batch, float *d_y, hc_stream stream);
+hc_status hc_mlp_backward(const uint16_t *d_params_bf16, const float *d_norm, const float *d_x,
+                          const float *d_target, const uint32_t *d_idx, uint32_t batch,
+                          float *d_grad, float *d_loss, void *d_scratch, size_t scratch_bytes,
+                          hc_stream stream);
+
+/* One Adam step (Kingma & Ba) at step t >= 1 on FP32 master weights, with bias
+ * correction; also writes the BF16 copy the kernels compute with (d_params_bf16,
+ * may be NULL; round to nearest even). */
+hc_status hc_adam_step(float *d_master, float *d_m, float *d_v, const float *d_grad, uint32_t np,
+                       uint32_t t, float lr, float beta1, float beta2, float eps,
+                       uint16_t *d_params_bf16, hc_stream stream);
+
+/* FP32 -> BF16, round to nearest even. */
+hc_status hc_to_bf16(const float *d_src, uint32_t n, uint16_t *d_dst, hc_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

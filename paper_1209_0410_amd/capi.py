@@ -49,6 +49,17 @@ SIGNATURES = {
     "hc_candidates": [_vp, _vp, _u32, _u32, _vp, _vp, _vp, _u32, _vp, _sz, _vp],
     "hc_brute_force_scratch_bytes": [_u64, _u32, _u32, ct.POINTER(_sz)],
     "hc_brute_force": [_vp, _u64, _vp, _u32, _u32, _vp, _vp, _vp, _sz, _vp],
+    "hc_index_ranks": [_vp, _vp, _vp],
+    "hc_labels": [_vp, _vp, _vp, _u32, _u32, _vp, _vp, _vp, _sz, _vp],
+    "hc_union_sizes": [_vp, _vp, _vp, _u32, _u32, _vp, _vp, _vp, _sz, _vp],
+    "hc_features": [_vp, _vp, _u32, _u32, _vp, _vp, _vp, _sz, _vp],
+    "hc_mlp_infer": [_vp, _vp, _vp, _u32, ct.c_float, _u32, _u32, _u32, _vp, _vp, _vp],
+    "hc_mlp_train_scratch_bytes": [_u32, ct.POINTER(_sz)],
+    "hc_mlp_forward": [_vp, _vp, _vp, _vp, _u32, _vp, _vp],
+    "hc_mlp_backward": [_vp, _vp, _vp, _vp, _vp, _u32, _vp, _vp, _vp, _sz, _vp],
+    "hc_adam_step": [_vp, _vp, _vp, _vp, _u32, _u32, ct.c_float, ct.c_float, ct.c_float,
+                     ct.c_float, _vp, _vp],
+    "hc_to_bf16": [_vp, _u32, _vp, _vp],
 }
 
 _LIB = None

@@ -1,0 +1,234 @@
+"""GPU parity of the learned-probe-depth kernels against the oracle.
+
+Integer outputs (ranks, labels, union sizes, the w decision away from its
+rounding boundary) are compared bit-exactly.  Floating-point outputs compare
+FP32 GPU results with the FP64 oracle on the same inputs:
+- features: |diff| <= 1e-4 + 1e-5 |ref| (FP32 log2 of exact integers);
+- MLP output: |diff| <= 1e-4 (1 + |ref|) (FP32 sums of 24-64 products);
+- gradients: |diff| <= 1e-3 max|g_ref| + 1e-6 (FP32 sums over the batch);
+- Adam: |diff| <= 1e-5 |ref| + 1e-7.
+The MLP runs on BF16 weights; the oracle gets the same BF16-rounded values."""
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+def u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def bf16_round(x):
+    """float32 -> BF16 (round to nearest even) -> float64, in numpy."""
+    u = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def setup(oracle):
+    import torch
+    from paper_1209_0410_amd import datagen
+    from paper_1209_0410_amd.index import Index, brute_force
+    from paper_1209_0410_amd import learned
+    db = datagen.make_db(30_000)
+    db[1000:1010] = db[5]                    # repeated rows: equal keys and distances
+    q = datagen.make_queries(400)
+    q[0] = db[5]
+    q[1] = 0
+    q[2] = 255
+    gdb = torch.from_numpy(db).cuda()
+    gq = torch.from_numpy(q).cuda()
+    gix = Index(gdb)
+    oix = oracle.Index(db)
+    rank = learned.ranks(gix)
+    return dict(db=db, q=q, gdb=gdb, gq=gq, gix=gix, oix=oix, rank=rank)
+
+
+def test_ranks_invert_the_lists(setup):
+    r = u32(setup["rank"])
+    oix = setup["oix"]
+    n = setup["db"].shape[0]
+    for c in range(8):
+        assert (r[oix.ids[c], c] == np.arange(n)).all()
+
+
+@pytest.mark.parametrize("k", [1, 10])
+def test_labels_bit_exact(setup, oracle, k):
+    from paper_1209_0410_amd.index import brute_force
+    from paper_1209_0410_amd import learned
+    gt, _ = brute_force(setup["gdb"], setup["gq"], k)
+    ot, _ = oracle.brute_force(setup["db"], setup["q"], k)
+    assert (u32(gt) == ot).all()
+    lab = u32(learned.labels(setup["gix"], setup["rank"], setup["gq"], gt))
+    assert (lab == setup["oix"].labels(setup["q"], k, ot)).all()
+
+
+@pytest.mark.parametrize("w", [1, 7, 64, 500, 5000, 40000])
+def test_union_sizes_bit_exact(setup, w):
+    from paper_1209_0410_amd import learned
+    q = setup["q"][:120]
+    got = u32(learned.union_sizes(setup["gix"], setup["rank"], setup["gq"][:120], w))
+    ref = np.array([len(c) for c in setup["oix"].candidates(q, w)])
+    assert (got == ref).all()
+
+
+def test_union_sizes_per_query_w(setup):
+    import torch
+    from paper_1209_0410_amd import learned
+    w = np.random.default_rng(4).integers(0, 3000, size=120).astype(np.uint32)
+    got = u32(learned.union_sizes(setup["gix"], setup["rank"], setup["gq"][:120], 0,
+                                  torch.from_numpy(w.view(np.int32)).cuda()))
+    ref = np.array([len(c) for c in setup["oix"].candidates(setup["q"][:120], w)])
+    assert (got == ref).all()
+
+
+def test_features_match_oracle(setup):
+    from paper_1209_0410_amd import learned
+    got = learned.features(setup["gix"], setup["gq"], 10).cpu().numpy().astype(np.float64)
+    ref = setup["oix"].features(setup["q"], 10)
+    assert np.isfinite(got).all()
+    assert (np.abs(got - ref) <= 1e-4 + 1e-5 * np.abs(ref)).all()
+
+
+def test_features_per_query_k(setup):
+    import torch
+    from paper_1209_0410_amd import learned
+    k = np.random.default_rng(5).choice([1, 10, 100], size=400).astype(np.uint32)
+    got = learned.features(setup["gix"], setup["gq"], 0,
+                           torch.from_numpy(k.view(np.int32)).cuda()).cpu().numpy()
+    assert np.allclose(got[:, 20], np.log2(k), atol=1e-6)
+
+
+def _params(seed):
+    from paper_1209_0410_amd import learned
+    p = learned.init_params(seed)
+    rng = np.random.default_rng(seed + 1)
+    p = p + rng.normal(0, 0.05, size=p.size).astype(np.float32)   # non-zero biases too
+    return p.astype(np.float32)
+
+
+def _norm(x):
+    mean = x.mean(0)
+    std = x.std(0) + 0.5
+    return mean.astype(np.float32), std.astype(np.float32)
+
+
+def test_mlp_forward_matches_oracle(oracle):
+    import torch
+    from paper_1209_0410_amd import learned
+    p = _params(3)
+    x = np.random.default_rng(6).normal(3, 2, size=(1000, 24)).astype(np.float32)
+    mean, std = _norm(x)
+    m = learned.WModel(torch.device("cuda:0"))
+    m.master = torch.from_numpy(p).cuda()
+    m.bf16 = learned.to_bf16(m.master)
+    m.norm = torch.from_numpy(np.concatenate([mean, std])).cuda()
+    got = m.predict(torch.from_numpy(x).cuda()).cpu().numpy().astype(np.float64)
+    xn = (x.astype(np.float64) - mean) / std
+    ref = oracle.mlp_forward(bf16_round(p), xn)
+    assert (np.abs(got - ref) <= 1e-4 * (1 + np.abs(ref))).all()
+
+
+@pytest.mark.parametrize("batch", [1, 257, 4096])
+def test_mlp_gradient_matches_oracle(oracle, batch):
+    import ctypes as ct
+    import torch
+    from paper_1209_0410_amd import capi, learned
+    from paper_1209_0410_amd.index import _empty_bytes, _ptr
+    p = _params(7)
+    rng = np.random.default_rng(8)
+    x = rng.normal(2, 3, size=(5000, 24)).astype(np.float32)
+    y = rng.normal(8, 2, size=5000).astype(np.float32)
+    idx = rng.choice(5000, size=batch, replace=False).astype(np.int32)
+    mean, std = _norm(x)
+    dev = torch.device("cuda:0")
+    bf = learned.to_bf16(torch.from_numpy(p).to(dev))
+    norm = torch.from_numpy(np.concatenate([mean, std])).to(dev)
+    gx, gy, gi = (torch.from_numpy(a).to(dev) for a in (x, y, idx))
+    grad = torch.zeros(5825, dtype=torch.float32, device=dev)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    sz = ct.c_size_t()
+    capi.call("hc_mlp_train_scratch_bytes", batch, ct.byref(sz))
+    sc = _empty_bytes(sz.value, dev)
+    stream = ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+    capi.call("hc_mlp_backward", _ptr(bf), _ptr(norm), _ptr(gx), _ptr(gy), _ptr(gi), batch,
+              _ptr(grad), _ptr(loss), _ptr(sc), sc.numel(), stream)
+    g = grad.cpu().numpy().astype(np.float64)
+    xn = (x[idx].astype(np.float64) - mean) / std
+    ref_loss, ref = oracle.mlp_loss_grad(bf16_round(p), xn, y[idx].astype(np.float64))
+    assert abs(float(loss.item()) - ref_loss) <= 1e-4 * (1 + ref_loss)
+    assert (np.abs(g - ref) <= 1e-3 * np.abs(ref).max() + 1e-6).all()
+    # deterministic: the same call gives the same bits
+    grad2 = torch.zeros_like(grad)
+    capi.call("hc_mlp_backward", _ptr(bf), _ptr(norm), _ptr(gx), _ptr(gy), _ptr(gi), batch,
+              _ptr(grad2), None, _ptr(sc), sc.numel(), stream)
+    assert torch.equal(grad, grad2)
+
+
+def test_adam_matches_oracle(oracle):
+    import torch
+    from paper_1209_0410_amd import capi
+    from paper_1209_0410_amd.index import _ptr
+    rng = np.random.default_rng(9)
+    theta = rng.normal(size=5825).astype(np.float32)
+    m = rng.normal(0, 0.1, size=5825).astype(np.float32)
+    v = rng.uniform(0, 0.1, size=5825).astype(np.float32)
+    g = rng.normal(size=5825).astype(np.float32)
+    gt, gm, gv, gg = (torch.from_numpy(a.copy()).cuda() for a in (theta, m, v, g))
+    bf = torch.zeros(5825, dtype=torch.int16, device="cuda")
+    import ctypes as ct
+    stream = ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+    capi.call("hc_adam_step", _ptr(gt), _ptr(gm), _ptr(gv), _ptr(gg), 5825, 7, 1e-3, 0.9,
+              0.999, 1e-8, _ptr(bf), stream)
+    ot, om, ov = (a.astype(np.float64) for a in (theta, m, v))
+    oracle.adam_step(ot, om, ov, g.astype(np.float64), 7, lr=1e-3)
+    for got, ref in [(gt, ot), (gm, om), (gv, ov)]:
+        got = got.cpu().numpy().astype(np.float64)
+        assert (np.abs(got - ref) <= 1e-5 * np.abs(ref) + 1e-7).all()
+    assert (bf16_round(gt.cpu().numpy()) ==
+            (bf.cpu().numpy().view(np.uint16).astype(np.uint32) << 16).view(np.float32)).all()
+
+
+def test_window_decision(oracle):
+    """w = clamp(ceil(2^(y + delta))): exact away from the rounding boundary,
+    one of the two neighbours on it; the fallback for non-finite y."""
+    import torch
+    from paper_1209_0410_amd import learned
+    p = _params(11)
+    x = np.random.default_rng(12).normal(0, 1, size=(3000, 24)).astype(np.float32)
+    m = learned.WModel(torch.device("cuda:0"), w_min=8, w_max=4096)
+    m.master = torch.from_numpy(p).cuda()
+    m.bf16 = learned.to_bf16(m.master)
+    gx = torch.from_numpy(x).cuda()
+    delta = 5.0
+    w = u32(m.windows(gx, delta))
+    y = oracle.mlp_forward(bf16_round(p), x.astype(np.float64)) + delta
+    e = 2.0 ** y
+    ref = np.clip(np.ceil(e), 8, 4096)
+    near = np.abs(e - np.round(e)) < 1e-3 * e
+    assert (w[~near] == ref[~near]).all()
+    assert (np.abs(w[near].astype(np.float64) - ref[near]) <= 1).all()
+    xs = x.copy()
+    xs[0, 0] = np.nan
+    w2 = u32(m.windows(torch.from_numpy(xs).cuda(), delta, w_fallback=77))
+    assert w2[0] == 77
+
+
+def test_training_reduces_loss(setup):
+    """A few GPU epochs on real labels lower the training loss."""
+    import torch
+    from paper_1209_0410_amd import learned
+    from paper_1209_0410_amd.index import brute_force
+    gix, gq = setup["gix"], setup["gq"]
+    truth, _ = brute_force(setup["gdb"], gq, 10)
+    lab = learned.labels(gix, setup["rank"], gq, truth)
+    f = learned.features(gix, gq, 10)
+    m = learned.WModel(torch.device("cuda:0"), seed=1, w_min=1, w_max=1 << 15)
+    m.set_norm(f)
+    y = m.targets(lab)
+    losses = m.train(f, y, epochs=40, batch=100, lr=3e-3, seed=2)
+    assert losses[-1] < 0.5 * losses[0]
