@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TARGET = 0.90
+CALIB_TARGET = 0.905    # margin for the sampling error of the evaluation recall
 
 
 def log(msg):
@@ -47,7 +48,7 @@ def parse():
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--sweep", default="16,64,256,1024,4096")
     ap.add_argument("--sweep-steps", type=int, default=3)
-    ap.add_argument("--recall-q", type=int, default=1000)
+    ap.add_argument("--recall-q", type=int, default=10_000)
     ap.add_argument("--calib-q", type=int, default=10_000)
     ap.add_argument("--train", type=int, default=200_000, help="0 = no learned w")
     ap.add_argument("--epochs", type=int, default=30)
@@ -55,6 +56,10 @@ def parse():
     ap.add_argument("--latency-batch", type=int, default=1000)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--w-fixed", type=int, default=0,
+                    help="use this fixed w instead of calibrating it (profiling runs)")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="also copy 1 GiB device-to-device 3 times (counter calibration)")
     return ap.parse_args()
 
 
@@ -135,6 +140,15 @@ def main():
 
     # ---- fixed-w sweep ---------------------------------------------------------
     rows = []
+    if a.copy_probe:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy probe: 3 x 1 GiB device-to-device")
+
     for w in sorted({int(x) for x in a.sweep.split(",") if x}):
         step_ms, kern_ms, wall_ms = timed(fixed_step(w), a.sweep_steps, 1)
         rec = recall_of(out[0])
@@ -153,8 +167,12 @@ def main():
     cq = datagen.make_queries(a.calib_q, seed=datagen.SEED_CALIB)
     gcq = torch.from_numpy(cq).to(dev)
     ctruth, _ = brute_force(gdb, gcq, k)
-    w_fix, rec_c = learned.calibrate_fixed_w(ix, gcq, ctruth, k, TARGET, hi=a.w_max)
-    log(f"calibrated fixed w = {w_fix} (calibration recall {rec_c:.4f})")
+    if a.w_fixed:
+        w_fix = a.w_fixed
+        log(f"fixed w = {w_fix} (given)")
+    else:
+        w_fix, rec_c = learned.calibrate_fixed_w(ix, gcq, ctruth, k, CALIB_TARGET, hi=a.w_max)
+        log(f"calibrated fixed w = {w_fix} (calibration recall {rec_c:.4f})")
     fs, fk, fwall = timed(fixed_step(w_fix), a.steps, a.warmup)
     f_rec = recall_of(out[0])
     f_uni = int(learned.union_sizes(ix, rank, gq, w_fix).cpu().numpy().view(np.uint32).sum())
@@ -169,16 +187,19 @@ def main():
         learned_row = run_learned(a, ix, rank, gdb, gq, gcq, ctruth, out, sc, timed, recall_of,
                                   alg_bytes, window_slots, dev)
 
-    head = learned_row if learned_row is not None else fixed
+    # headline: the faster method whose evaluation recall meets the target
+    eligible = [r for r in (fixed, learned_row) if r is not None and r["recall"] >= TARGET]
+    head = max(eligible, key=lambda r: r["qps"]) if eligible else fixed
+    use_learned = head is learned_row
 
     # ---- batch latency of the headline method ------------------------------------
     lb = min(a.latency_batch, a.nq)
     lat = []
-    for i in range(0, a.nq - lb + 1, lb):
+    for i in range(0, a.nq - lb + 1, lb) if lb > 0 else []:
         sub = gq[i:i + lb]
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        if learned_row is not None:
+        if use_learned:
             learned.search_learned(ix, head["_model"], sub, k,
                                    (out[0][i:i + lb], out[1][i:i + lb]), sc)
         else:
@@ -186,8 +207,9 @@ def main():
         e1.record(stream)
         lat.append((e0, e1))
     torch.cuda.synchronize()
-    lat_ms = np.array([e0.elapsed_time(e1) for e0, e1 in lat])
-    head.pop("_model", None)
+    lat_ms = np.array([e0.elapsed_time(e1) for e0, e1 in lat] or [float("nan")])
+    if learned_row is not None:
+        learned_row.pop("_model", None)
 
     cpu = None
     if a.cpu_baseline:
@@ -208,10 +230,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"Multicurves search on one GPU: N={a.n} mixture uint8 d=128, "
                                f"8 curves x 16 dims, Q={a.nq} per batch, k={k}, "
-                               f"{'learned' if learned_row else 'fixed'} w at recall@10>=0.90",
+                               f"{'learned' if use_learned else 'fixed'} w calibrated to "
+                               f"recall@10>=0.90",
                    "n": a.n, "nq": a.nq, "k": k, "curves": 8,
-                   "method": "learned-w" if learned_row else "fixed-w"},
+                   "method": "learned-w" if use_learned else "fixed-w"},
         "recall_at_10": head["recall"],
+        "recall_target_met": bool(head["recall"] >= TARGET),
         "recall_queries": rq,
         "fixed_w": fixed,
         "learned_w": learned_row,
@@ -256,7 +280,7 @@ def run_learned(a, ix, rank, gdb, gq, gcq, ctruth, out, sc, timed, recall_of, al
     train_s = time.time() - t0
     log(f"trained {a.epochs} epochs in {train_s:.1f}s, loss {losses[0]:.3f} -> {losses[-1]:.3f}")
     cfeats = learned.features(ix, gcq, k)
-    delta, rec_c = learned.calibrate_delta(ix, model, gcq, cfeats, ctruth, k, TARGET)
+    delta, rec_c = learned.calibrate_delta(ix, model, gcq, cfeats, ctruth, k, CALIB_TARGET)
     model.delta = delta
     log(f"calibrated delta = {delta:.3f} (calibration recall {rec_c:.4f})")
     feats_b = torch.empty((a.nq, learned.FEATURES), dtype=torch.float32, device=dev)
