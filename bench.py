@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--w-fixed", type=int, default=0,
                     help="use this fixed w instead of calibrating it (profiling runs)")
+    ap.add_argument("--uneven", type=int, default=200_000,
+                    help="queries of the uneven batch (per-query w and k); 0 = skip")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also copy 1 GiB device-to-device 3 times (counter calibration)")
     return ap.parse_args()
@@ -211,6 +213,8 @@ def main():
     if learned_row is not None:
         learned_row.pop("_model", None)
 
+    uneven = run_uneven(a, ix, rank, gdb, dev) if a.uneven else None
+
     cpu = None
     if a.cpu_baseline:
         cpu = cpu_baseline(db, q, k, w_fix, a.cpu_seconds)
@@ -244,12 +248,18 @@ def main():
                        "p99": float(np.percentile(lat_ms, 99))},
         "build_s": build_s,
         "sweep": rows,
+        "uneven": uneven,
         "roofline": {"bound": "hbm", "achieved": head["alg_GBs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": head["alg_GBs"] / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_stream (hc_search_encoded)",
                      "kernel_ms": head["kernel_ms"],
                      "alg_bytes_per_launch": head["alg_bytes"]},
     }
+    if head is fixed:
+        tb, tsrc = counted_traffic(a.n, a.nq, k, w_fix)
+        if tb is not None:
+            result["roofline"]["traffic"] = tb
+            result["roofline"]["traffic_source"] = tsrc
     if cpu is not None:
         result["cpu_baseline"] = cpu
     print(json.dumps(result), flush=True)
@@ -308,6 +318,82 @@ def run_learned(a, ix, rank, gdb, gq, gcq, ctruth, out, sc, timed, recall_of, al
     log(f"learned: {ls:.3f} ms/step, {row['qps']:.3e} q/s, recall {rec:.4f}, mean w "
         f"{row['mean_w']:.0f}")
     row["_model"] = model
+    return row
+
+
+def counted_traffic(n, nq, k, w):
+    """HBM bytes per search launch from the committed rocprofv3 counter summary of
+    this workload, if its kernel sources are the ones built here; else None."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_1209_0410_amd", "csrc")
+    md5 = hashlib.md5(b"".join(open(os.path.join(src, f), "rb").read()
+                                for f in ("hc_search.hip", "hc_device.h"))).hexdigest()
+    want = f"workload: n={n} nq={nq} k={k} w={w}"
+    for path in glob.glob(os.path.join(ROOT, "profiles", "k_stream_*_counters.md")):
+        text = open(path).read()
+        if want not in text or f"kernel_sources_md5: {md5}" not in text:
+            continue
+        for line in text.splitlines():
+            if line.startswith("traffic_bytes_per_launch:"):
+                return float(line.split(":")[1]), os.path.relpath(path, ROOT)
+    return None, None
+
+
+def run_uneven(a, ix, rank, gdb, dev):
+    """Uneven batch: w log-uniform in [8, 512] and k from {1, 10, 100} per query,
+    one autotuned persistent launch, captured in a HIP graph and replayed."""
+    import torch
+    from paper_1209_0410_amd import datagen, learned
+    from paper_1209_0410_amd.index import brute_force
+    from paper_1209_0410_amd.tune import Graph, Tuner
+    nq = a.uneven
+    q = datagen.make_queries(nq, seed=datagen.SEED_UNEVEN)
+    w, k = datagen.uneven_w_k(nq)
+    gq = torch.from_numpy(q).to(dev)
+    gw = torch.from_numpy(w.view(np.int32)).to(dev)
+    gk = torch.from_numpy(k.view(np.int32)).to(dev)
+    kst = int(k.max())
+    t0 = time.time()
+    cfg, entry = Tuner().best(ix, gq, gw, gk, sample=min(nq, 20000))
+    log(f"uneven: tuned {entry['tried']} shapes in {time.time() - t0:.1f}s: "
+        f"chunk={cfg.chunk_slots} split={cfg.max_split} per_cu={cfg.blocks_per_cu} "
+        f"({entry['ms']:.3f} ms vs default {entry['default_ms']:.3f} ms on {entry['sample']})")
+    sc = ix.uneven_scratch(nq, kst, cfg)
+    out = (torch.empty((nq, kst), dtype=torch.int32, device=dev),
+           torch.empty((nq, kst), dtype=torch.int32, device=dev))
+    g = Graph(lambda: ix.search_uneven(gq, w_per_query=gw, k_per_query=gk, k_stride=kst,
+                                       cfg=cfg, out=out, scratch=sc))
+    for _ in range(a.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(a.steps)]
+    for e0, e1 in ev:
+        e0.record()
+        g.replay()
+        e1.record()
+    torch.cuda.synchronize()
+    ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
+    uni = int(learned.union_sizes(ix, rank, gq, 0, gw).cpu().numpy().view(np.uint32).sum())
+    pos = ix.positions(gq).cpu().numpy().view(np.uint32).astype(np.int64)
+    wl = w.astype(np.int64)[:, None]
+    slots = int((np.minimum(pos + wl, a.n) - np.maximum(pos - wl, 0)).sum())
+    ab = 4 * slots + 128 * uni + 8 * int(k.sum())
+    # recall@min(k, 10) on the first queries (exact kNN with k = 10)
+    m = min(nq, 2000)
+    tid, _ = brute_force(gdb, gq[:m].contiguous(), 10)
+    truth = tid.cpu().numpy().view(np.uint32)
+    got = out[0][:m].cpu().numpy().view(np.uint32)
+    hits = [len(set(got[i, :min(int(k[i]), 10)].tolist()) & set(truth[i, :min(int(k[i]), 10)].tolist()))
+            / min(int(k[i]), 10) for i in range(m)]
+    row = dict(nq=nq, ms_per_batch=ms, qps=nq / ms * 1e3, mean_w=float(w.mean()),
+               k_mix={str(v): int((k == v).sum()) for v in np.unique(k)},
+               cfg=[cfg.chunk_slots, cfg.max_split, cfg.blocks_per_cu], tune=entry,
+               union_per_query=uni / nq, alg_bytes=ab, alg_GBs=ab / (ms * 1e-3) / 1e9,
+               recall_at_min_k_10=float(np.mean(hits)), graph=True)
+    log(f"uneven: {ms:.3f} ms per batch of {nq}, {row['qps']:.3e} q/s, "
+        f"{row['alg_GBs']:.0f} GB/s, recall@min(k,10) {row['recall_at_min_k_10']:.4f}")
     return row
 
 

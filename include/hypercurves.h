@@ -155,6 +155,35 @@ hc_status hc_search_encoded(const hc_index *idx, const uint8_t *d_queries, uint3
                             uint32_t *d_out_ids, uint32_t *d_out_dists,
                             void *d_scratch, size_t scratch_bytes, hc_stream stream);
 
+/* Uneven batches: every query has its own w and its own k.  A query's window
+ * slots (up to 16 w) are cut into work items of at most chunk_slots slots
+ * (at most max_split items per query; the chunk grows beyond that); a
+ * persistent grid of wavefronts takes items from a counter in scratch, and a
+ * merge kernel combines the items of a query, dropping repeated ids.  Nothing
+ * waits on the host, so the call may be captured in a HIP graph.
+ * Fields set to 0 take defaults: chunk_slots 8192, max_split 32,
+ * blocks_per_cu = the occupancy limit of the work kernel. */
+typedef struct {
+    uint32_t chunk_slots;
+    uint32_t max_split;
+    uint32_t blocks_per_cu;
+} hc_uneven_cfg;
+
+hc_status hc_uneven_scratch_bytes(const hc_index *idx, uint32_t nq, uint32_t k_stride,
+                                  const hc_uneven_cfg *cfg, size_t *bytes);
+
+/* Alg. 2 per query with w = d_w[q] (or w_fixed) and k = d_k[q] (or k_fixed;
+ * device entries are clamped to [1, k_stride]).  Row q of d_out_ids /
+ * d_out_dists (nq x k_stride) holds the query's k results then 0xFFFFFFFF up
+ * to k_stride.  1 <= k_stride <= HC_K_MAX.  d_scratch must be 256-byte aligned
+ * and hc_uneven_scratch_bytes long (it holds the query keys, positions, item
+ * offsets, the work counter and nq * max_split * k_stride partial results). */
+hc_status hc_search_uneven(const hc_index *idx, const uint8_t *d_queries, uint32_t nq,
+                           uint32_t w_fixed, const uint32_t *d_w, uint32_t k_fixed,
+                           const uint32_t *d_k, uint32_t k_stride, uint32_t *d_out_ids,
+                           uint32_t *d_out_dists, void *d_scratch, size_t scratch_bytes,
+                           const hc_uneven_cfg *cfg, hc_stream stream);
+
 /* ---------------------------------------------------------------------- */
 /* Parity / inspection exports: the same kernels, stopping early           */
 /* ---------------------------------------------------------------------- */

@@ -10,7 +10,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhypercurves.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["hc_encode.hip", "hc_build.hip", "hc_search.hip", "hc_brute.hip", "hc_learn.hip"]
+SOURCES = ["hc_encode.hip", "hc_build.hip", "hc_search.hip", "hc_brute.hip", "hc_learn.hip",
+           "hc_uneven.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -20,6 +20,11 @@ class HcError(RuntimeError):
         super().__init__(f"{name} failed: {status_str(status)} ({status})")
 
 
+class hc_uneven_cfg(ct.Structure):
+    _fields_ = [("chunk_slots", ct.c_uint32), ("max_split", ct.c_uint32),
+                ("blocks_per_cu", ct.c_uint32)]
+
+
 class hc_params(ct.Structure):
     _fields_ = [("dim", ct.c_uint32), ("curves", ct.c_uint32),
                 ("dims_per_curve", ct.c_uint32), ("bits", ct.c_uint32),
@@ -60,6 +65,9 @@ SIGNATURES = {
     "hc_adam_step": [_vp, _vp, _vp, _vp, _u32, _u32, ct.c_float, ct.c_float, ct.c_float,
                      ct.c_float, _vp, _vp],
     "hc_to_bf16": [_vp, _u32, _vp, _vp],
+    "hc_uneven_scratch_bytes": [_vp, _u32, _u32, ct.POINTER(hc_uneven_cfg), ct.POINTER(_sz)],
+    "hc_search_uneven": [_vp, _vp, _u32, _u32, _vp, _u32, _vp, _u32, _vp, _vp, _vp, _sz,
+                         ct.POINTER(hc_uneven_cfg), _vp],
 }
 
 _LIB = None

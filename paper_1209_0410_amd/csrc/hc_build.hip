@@ -13,13 +13,13 @@
 #include <vector>
 
 #include "hc_hilbert.h"
+#include "hc_scan.h"
 
 namespace hc {
 
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;   // 4096 keys per tile
-constexpr int kScanThreads = 1024;
 
 __device__ inline uint32_t key_digit(const Key &k, int d)
 {
@@ -85,61 +85,6 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_hist(const Key *keys, uin
     }
     __syncthreads();
     counts[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
-}
-
-// Exclusive prefix sum of a wave's values; *total receives the wave's sum.
-__device__ inline uint32_t wave_excl_scan(uint32_t v, uint32_t *total)
-{
-    const int lane = threadIdx.x & 63;
-    uint32_t x = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
-    }
-    *total = __shfl(x, 63, 64);
-    return x - v;
-}
-
-// In-place exclusive prefix sum of n values, one block of kScanThreads.
-__global__ __launch_bounds__(kScanThreads) void k_scan_excl(uint32_t *a, uint64_t n)
-{
-    __shared__ uint32_t wsum[kScanThreads / 64];
-    __shared__ uint32_t carry_s;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    if (tid == 0) carry_s = 0;
-    __syncthreads();
-    for (uint64_t base = 0; base < n; base += (uint64_t)kScanThreads * 4) {
-        uint32_t v[4];
-        uint32_t s = 0;
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const uint64_t i = base + (uint64_t)tid * 4 + j;
-            v[j] = i < n ? a[i] : 0u;
-            s += v[j];
-        }
-        uint32_t wt;
-        uint32_t ex = wave_excl_scan(s, &wt);
-        if (lane == 0) wsum[wave] = wt;
-        __syncthreads();
-        if (wave == 0) {
-            uint32_t t = lane < kScanThreads / 64 ? wsum[lane] : 0u;
-            uint32_t tot;
-            uint32_t e = wave_excl_scan(t, &tot);
-            if (lane < kScanThreads / 64) wsum[lane] = e;
-        }
-        __syncthreads();
-        uint32_t run = carry_s + wsum[wave] + ex;
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const uint64_t i = base + (uint64_t)tid * 4 + j;
-            if (i < n) a[i] = run;
-            run += v[j];
-        }
-        __syncthreads();
-        if (tid == kScanThreads - 1) carry_s = run;
-        __syncthreads();
-    }
 }
 
 // Stable scatter of one digit pass.  Within a tile, keys are visited in order:

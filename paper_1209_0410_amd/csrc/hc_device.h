@@ -82,4 +82,266 @@ __device__ inline void locate(const IndexView &v, const Key *qk_row, uint32_t fi
     }
 }
 
+// Sum over 16 bytes of (q - x)^2 = q.q + x.x - 2 q.x with 4-byte dot products
+// (every term is exact in uint32).
+__device__ inline uint32_t sqdist16(const uint4 &q, uint32_t qq, const uint4 &x)
+{
+    uint32_t xx = __builtin_amdgcn_udot4(x.x, x.x, 0u, false);
+    xx = __builtin_amdgcn_udot4(x.y, x.y, xx, false);
+    xx = __builtin_amdgcn_udot4(x.z, x.z, xx, false);
+    xx = __builtin_amdgcn_udot4(x.w, x.w, xx, false);
+    uint32_t qx = __builtin_amdgcn_udot4(q.x, x.x, 0u, false);
+    qx = __builtin_amdgcn_udot4(q.y, x.y, qx, false);
+    qx = __builtin_amdgcn_udot4(q.z, x.z, qx, false);
+    qx = __builtin_amdgcn_udot4(q.w, x.w, qx, false);
+    return qq + xx - 2u * qx;
+}
+
+// Inserts x into an ascending register list unless the list holds it already
+// (unrolled: static register indexing only).
+template <int KR>
+__device__ inline void insert_distinct(uint64_t (&L)[KR], uint64_t x)
+{
+    if (x < L[KR - 1]) {
+        bool dup = false;
+#pragma unroll
+        for (int i = 0; i < KR; i++) dup |= (L[i] == x);
+        if (!dup) {
+#pragma unroll
+            for (int i = KR - 1; i > 0; i--)
+                L[i] = x < L[i - 1] ? L[i - 1] : (x < L[i] ? x : L[i]);
+            L[0] = x < L[0] ? x : L[0];
+        }
+    }
+}
+
+// Merges two ascending lists (kNone = empty) into the first k distinct keys.
+// Either list may repeat a key.  Run by one lane.
+__device__ inline void merge_distinct(const uint64_t *a, uint32_t na, const uint64_t *b,
+                                      uint32_t nb, uint32_t k, uint64_t *out)
+{
+    uint32_t i = 0, j = 0, o = 0;
+    uint64_t last = kNone;
+    while (o < k) {
+        const uint64_t x = i < na ? a[i] : kNone;
+        const uint64_t y = j < nb ? b[j] : kNone;
+        const uint64_t m = x < y ? x : y;
+        if (m == kNone) break;
+        if (x == m) i++;
+        if (y == m) j++;
+        if (m != last) {
+            out[o++] = m;
+            last = m;
+        }
+    }
+    for (; o < k; o++) out[o] = kNone;
+}
+
+constexpr int kBuf = 1024;   // LDS buffer of the k > 16 top-k
+
+// LDS of one wavefront's top-k for k > 16.
+struct TopKShared {
+    uint64_t buf[kBuf];
+    uint64_t run[HC_K_MAX];
+    uint64_t out[HC_K_MAX];
+};
+
+// The k smallest distinct packed keys (dist << 32 | id) pushed by a wavefront,
+// 64 keys (one per lane) per push.
+//  KR > 0: every lane keeps an ascending register list of KR keys that refuses
+//          a key it holds; k <= KR.
+//  KR = 0: keys below the current k-th distinct key collect in an LDS buffer
+//          that is bitonic-sorted and merged into the running list when full.
+template <int KR>
+struct WaveTopK {
+    static constexpr int NL = KR > 0 ? KR : 1;
+    uint64_t L[NL];
+    uint32_t k, nbuf;
+    uint64_t tau;
+    TopKShared *sh;
+
+    __device__ void init(uint32_t k_, TopKShared *sh_, int lane)
+    {
+        k = k_;
+        sh = sh_;
+        nbuf = 0;
+        tau = kNone;
+#pragma unroll
+        for (int i = 0; i < NL; i++) L[i] = kNone;
+        if (KR == 0) {
+            for (uint32_t i = lane; i < k; i += 64) sh->run[i] = kNone;
+            __syncthreads();
+        }
+    }
+
+    __device__ void flush(int lane)
+    {
+        __syncthreads();
+        for (uint32_t i = nbuf + lane; i < (uint32_t)kBuf; i += 64) sh->buf[i] = kNone;
+        __syncthreads();
+        for (uint32_t size = 2; size <= (uint32_t)kBuf; size <<= 1) {
+            for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+                for (uint32_t i = lane; i < (uint32_t)kBuf / 2; i += 64) {
+                    const uint32_t lo = 2 * stride * (i / stride) + (i % stride);
+                    const uint32_t hi = lo + stride;
+                    const bool up = (lo & size) == 0;
+                    const uint64_t x0 = sh->buf[lo], x1 = sh->buf[hi];
+                    if ((x0 > x1) == up) {
+                        sh->buf[lo] = x1;
+                        sh->buf[hi] = x0;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if (lane == 0) {
+            merge_distinct(sh->run, k, sh->buf, nbuf, k, sh->out);
+            for (uint32_t i = 0; i < k; i++) sh->run[i] = sh->out[i];
+        }
+        __syncthreads();
+        tau = sh->run[k - 1];
+        nbuf = 0;
+    }
+
+    // wave-collective
+    __device__ void push(uint64_t key, int lane)
+    {
+        if constexpr (KR > 0) {
+            insert_distinct<NL>(L, key);
+        } else {
+            const bool pass = key < tau;
+            const uint64_t m = __ballot(pass);
+            if (pass) sh->buf[nbuf + lanes_below64(m)] = key;
+            nbuf += (uint32_t)__popcll(m);
+            if (nbuf > (uint32_t)(kBuf - 64)) flush(lane);
+        }
+    }
+
+    // wave-collective: key j of the result (kNone = empty) for j < k goes to
+    // write(j, key), called by one lane per j.
+    template <class F>
+    __device__ void finish(int lane, F write)
+    {
+        if constexpr (KR > 0) {
+            uint64_t mykey = kNone;
+            for (uint32_t j = 0; j < k; j++) {
+                const uint64_t m = wave_min_u64(L[0]);
+                if ((uint32_t)lane == j) mykey = m;
+                if (m != kNone && L[0] == m) {   // every lane holding m pops it
+#pragma unroll
+                    for (int i = 0; i < NL - 1; i++) L[i] = L[i + 1];
+                    L[NL - 1] = kNone;
+                }
+            }
+            if ((uint32_t)lane < k) write((uint32_t)lane, mykey);
+        } else {
+            if (nbuf) flush(lane);
+            for (uint32_t i = lane; i < k; i += 64) write(i, sh->run[i]);
+        }
+    }
+};
+
+// The window slots of one query, all curves concatenated: curve c's window
+// starts at list place lo_c and occupies slots [off_c, off_{c+1}).
+struct WindowSet {
+    const uint32_t *base[kMaxCurves + 1];   // &ids_c[lo_c]
+    uint64_t off[kMaxCurves + 1];
+};
+
+// Fills ws (LDS) from the query's positions; returns the number of slots.
+// Wave-collective (writes by lanes 0..8, then a barrier).
+__device__ inline uint64_t make_windows(const IndexView &v, const uint64_t (&pos)[kMaxCurves],
+                                        uint64_t w, int lane, WindowSet *ws)
+{
+    uint64_t total = 0;
+#pragma unroll
+    for (int c = 0; c < kMaxCurves; c++) {
+        uint64_t lo = 0, cnt = 0;
+        if (c < (int)v.curves) {
+            lo = pos[c] > w ? pos[c] - w : 0;
+            const uint64_t hi = pos[c] + w < v.n ? pos[c] + w : v.n;
+            cnt = hi - lo;
+        }
+        if (lane == c) {
+            ws->base[c] = c < (int)v.curves ? v.ids[c] + lo : nullptr;
+            ws->off[c] = total;
+        }
+        total += cnt;
+    }
+    if (lane == kMaxCurves) {
+        ws->base[kMaxCurves] = nullptr;
+        ws->off[kMaxCurves] = total;
+    }
+    __syncthreads();
+    return total;
+}
+
+// Streams slots [s0, s1) of a query's windows through the distance kernel:
+// per step, one coalesced load of 64 window ids, then 8 lanes per 128-byte
+// row (16-byte loads), dot4 arithmetic and a 3-step lane-xor reduction; each
+// lane ends up with one slot's packed key, handed to sink.push (kNone past s1).
+template <int G, class Sink>
+__device__ inline void stream_slots(const uint8_t *db, const WindowSet *ws, uint64_t s0,
+                                    uint64_t s1, const uint4 &qv, uint32_t qq, int lane,
+                                    Sink &sink)
+{
+    const int part = lane & 7;
+    uint64_t off[kMaxCurves];   // uniform copies of the prefix sums
+#pragma unroll
+    for (int c = 0; c < kMaxCurves; c++) off[c] = ws->off[c];
+    for (uint64_t base = s0; base < s1; base += 64 * G) {
+        uint32_t myid[G];
+#pragma unroll
+        for (int g = 0; g < G; g++) {
+            const uint64_t s = base + 64 * g + lane;
+            myid[g] = 0;
+            if (s < s1) {
+                int c = 0;
+#pragma unroll
+                for (int j = 1; j < kMaxCurves; j++) c += s >= off[j] ? 1 : 0;
+                myid[g] = ws->base[c][s - ws->off[c]];
+            }
+        }
+        // in step t of group g, lanes 8r..8r+7 read the row of slot 64 g + 8 t + r
+        uint4 x[8 * G];
+#pragma unroll
+        for (int g = 0; g < G; g++)
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                const uint32_t rid = __shfl(myid[g], 8 * t + (lane >> 3), 64);
+                const uint64_t s = base + 64 * g + 8 * t + (lane >> 3);
+                x[8 * g + t] = s < s1
+                    ? *reinterpret_cast<const uint4 *>(db + (uint64_t)rid * kDim + 16 * part)
+                    : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+        for (int g = 0; g < G; g++) {
+            uint32_t mine = 0;
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                uint32_t d = sqdist16(qv, qq, x[8 * g + t]);
+                d += __shfl_xor(d, 1, 64);
+                d += __shfl_xor(d, 2, 64);
+                d += __shfl_xor(d, 4, 64);
+                if (part == t) mine = d;
+            }
+            const uint32_t mid = __shfl(myid[g], 8 * part + (lane >> 3), 64);
+            // this lane now holds slot base + 64 g + 8 part + (lane >> 3)
+            const uint64_t s = base + 64 * g + 8 * part + (lane >> 3);
+            sink.push(s < s1 ? (((uint64_t)mine << 32) | mid) : kNone, lane);
+        }
+    }
+}
+
+// This lane's 16-byte part of query row q, and that part's q.q.
+__device__ inline void query_part(const uint8_t *queries, uint32_t q, int lane, uint4 &qv,
+                                  uint32_t &qq)
+{
+    qv = *reinterpret_cast<const uint4 *>(queries + (uint64_t)q * kDim + 16 * (lane & 7));
+    qq = __builtin_amdgcn_udot4(qv.x, qv.x, 0u, false) +
+         __builtin_amdgcn_udot4(qv.y, qv.y, 0u, false) +
+         __builtin_amdgcn_udot4(qv.z, qv.z, 0u, false) +
+         __builtin_amdgcn_udot4(qv.w, qv.w, 0u, false);
+}
+
 }  // namespace hc

@@ -1,0 +1,66 @@
+// Single-block exclusive prefix sum, shared by the index build and the uneven
+// search (each translation unit gets its own copy of the kernel).
+#pragma once
+
+#include "hc_internal.h"
+
+namespace hc {
+
+constexpr int kScanThreads = 1024;
+
+// Exclusive prefix sum of a wave's values; *total receives the wave's sum.
+static __device__ inline uint32_t wave_excl_scan(uint32_t v, uint32_t *total)
+{
+    const int lane = threadIdx.x & 63;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    *total = __shfl(x, 63, 64);
+    return x - v;
+}
+
+// In-place exclusive prefix sum of n values, one block of kScanThreads.
+static __global__ __launch_bounds__(kScanThreads) void k_scan_excl(uint32_t *a, uint64_t n)
+{
+    __shared__ uint32_t wsum[kScanThreads / 64];
+    __shared__ uint32_t carry_s;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    if (tid == 0) carry_s = 0;
+    __syncthreads();
+    for (uint64_t base = 0; base < n; base += (uint64_t)kScanThreads * 4) {
+        uint32_t v[4];
+        uint32_t s = 0;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint64_t i = base + (uint64_t)tid * 4 + j;
+            v[j] = i < n ? a[i] : 0u;
+            s += v[j];
+        }
+        uint32_t wt;
+        uint32_t ex = wave_excl_scan(s, &wt);
+        if (lane == 0) wsum[wave] = wt;
+        __syncthreads();
+        if (wave == 0) {
+            uint32_t t = lane < kScanThreads / 64 ? wsum[lane] : 0u;
+            uint32_t tot;
+            uint32_t e = wave_excl_scan(t, &tot);
+            if (lane < kScanThreads / 64) wsum[lane] = e;
+        }
+        __syncthreads();
+        uint32_t run = carry_s + wsum[wave] + ex;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint64_t i = base + (uint64_t)tid * 4 + j;
+            if (i < n) a[i] = run;
+            run += v[j];
+        }
+        __syncthreads();
+        if (tid == kScanThreads - 1) carry_s = run;
+        __syncthreads();
+    }
+}
+
+}  // namespace hc

@@ -32,7 +32,6 @@
 namespace hc {
 
 constexpr int kKR = 16;                 // longest register list (k <= 16)
-constexpr int kBuf = 1024;              // LDS buffer of the k > 16 path
 constexpr uint32_t kMaxSetSlots = 4096; // union capacity of the set kernel
 constexpr int kIdBatch = 16;            // set kernel: ids loaded before inserting
 
@@ -50,235 +49,43 @@ struct SearchArgs {
     uint32_t cs_log2;          // set kernel: union capacity = 1 << cs_log2
 };
 
-// Sum over 16 bytes of (q - x)^2 = q.q + x.x - 2 q.x with 4-byte dot products
-// (every term is exact in uint32).
-__device__ inline uint32_t sqdist16(const uint4 &q, uint32_t qq, const uint4 &x)
-{
-    uint32_t xx = __builtin_amdgcn_udot4(x.x, x.x, 0u, false);
-    xx = __builtin_amdgcn_udot4(x.y, x.y, xx, false);
-    xx = __builtin_amdgcn_udot4(x.z, x.z, xx, false);
-    xx = __builtin_amdgcn_udot4(x.w, x.w, xx, false);
-    uint32_t qx = __builtin_amdgcn_udot4(q.x, x.x, 0u, false);
-    qx = __builtin_amdgcn_udot4(q.y, x.y, qx, false);
-    qx = __builtin_amdgcn_udot4(q.z, x.z, qx, false);
-    qx = __builtin_amdgcn_udot4(q.w, x.w, qx, false);
-    return qq + xx - 2u * qx;
-}
-
-// Inserts x into an ascending register list unless the list holds it already
-// (unrolled: static register indexing only).
-template <int KR>
-__device__ inline void insert_distinct(uint64_t (&L)[KR], uint64_t x)
-{
-    if (x < L[KR - 1]) {
-        bool dup = false;
-#pragma unroll
-        for (int i = 0; i < KR; i++) dup |= (L[i] == x);
-        if (!dup) {
-#pragma unroll
-            for (int i = KR - 1; i > 0; i--)
-                L[i] = x < L[i - 1] ? L[i - 1] : (x < L[i] ? x : L[i]);
-            L[0] = x < L[0] ? x : L[0];
-        }
-    }
-}
-
-// Merges two ascending lists (kNone = empty) into the first k distinct keys.
-// Either list may repeat a key.  Run by one lane.
-__device__ inline void merge_distinct(const uint64_t *a, uint32_t na, const uint64_t *b,
-                                      uint32_t nb, uint32_t k, uint64_t *out)
-{
-    uint32_t i = 0, j = 0, o = 0;
-    uint64_t last = kNone;
-    while (o < k) {
-        const uint64_t x = i < na ? a[i] : kNone;
-        const uint64_t y = j < nb ? b[j] : kNone;
-        const uint64_t m = x < y ? x : y;
-        if (m == kNone) break;
-        if (x == m) i++;
-        if (y == m) j++;
-        if (m != last) {
-            out[o++] = m;
-            last = m;
-        }
-    }
-    for (; o < k; o++) out[o] = kNone;
-}
-
 // ---------------------------------------------------------------------------
 // Search kernel
 // ---------------------------------------------------------------------------
 
 // G: 64-slot groups a wave loads per iteration (rows in flight per lane = 8G).
+// KR: register list length (k <= KR), or 0 for the LDS path (k > 16).
 // At least 5 waves per SIMD (<= 102 VGPRs) unless the 16-entry list would spill.
-template <int KR, int G, bool BIGK>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((KR > 10 || BIGK) ? 4 : 5)))
+template <int KR, int G>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((KR > 10 || KR == 0) ? 4 : 5)))
 void k_stream(SearchArgs a)
 {
-    __shared__ const uint32_t *s_base[kMaxCurves + 1];   // &ids_c[lo_c]
-    __shared__ uint64_t s_off[kMaxCurves + 1];           // window prefix sums
-    __shared__ uint64_t s_buf[BIGK ? kBuf : 1];
-    __shared__ uint64_t s_run[BIGK ? HC_K_MAX : 1];
-    __shared__ uint64_t s_out[BIGK ? HC_K_MAX : 1];
-
+    __shared__ WindowSet ws;
+    TopKShared *tks = nullptr;
+    if constexpr (KR == 0) {
+        __shared__ TopKShared sh;
+        tks = &sh;
+    }
     const int lane = threadIdx.x;
     const uint32_t q = blockIdx.x;
     if (q >= a.nq) return;
-    const uint32_t C = a.v.curves;
-    const uint64_t n = a.v.n;
-    const uint32_t k = a.k;
-
-    // this lane's 16-byte part of the query row
-    const int part = lane & 7;
-    const uint4 qv = *reinterpret_cast<const uint4 *>(a.queries + (uint64_t)q * kDim + 16 * part);
-    const uint32_t qq = __builtin_amdgcn_udot4(qv.x, qv.x, 0u, false) +
-                        __builtin_amdgcn_udot4(qv.y, qv.y, 0u, false) +
-                        __builtin_amdgcn_udot4(qv.z, qv.z, 0u, false) +
-                        __builtin_amdgcn_udot4(qv.w, qv.w, 0u, false);
+    uint4 qv;
+    uint32_t qq;
+    query_part(a.queries, q, lane, qv, qq);
     const uint64_t w = a.d_w ? a.d_w[q] : a.w_fixed;
 
-    // ---- 1-2. positions and windows ----------------------------------------
     uint64_t pos[kMaxCurves];
-    locate<kMaxCurves>(a.v, a.qkeys + (uint64_t)q * C, 0, 1, lane, pos);
-    uint64_t total = 0;
-#pragma unroll
-    for (int c = 0; c < kMaxCurves; c++) {
-        uint64_t lo = 0, cnt = 0;
-        if (c < (int)C) {
-            lo = pos[c] > w ? pos[c] - w : 0;
-            const uint64_t hi = pos[c] + w < n ? pos[c] + w : n;
-            cnt = hi - lo;
-        }
-        if (lane == c) {
-            s_base[c] = c < (int)C ? a.v.ids[c] + lo : nullptr;
-            s_off[c] = total;
-        }
-        total += cnt;
-    }
-    if (lane == kMaxCurves) {
-        s_base[kMaxCurves] = nullptr;
-        s_off[kMaxCurves] = total;
-    }
-    __syncthreads();
-    uint64_t off[kMaxCurves];   // uniform copies of the prefix sums
-#pragma unroll
-    for (int c = 0; c < kMaxCurves; c++) off[c] = s_off[c];
+    locate<kMaxCurves>(a.v, a.qkeys + (uint64_t)q * a.v.curves, 0, 1, lane, pos);
+    const uint64_t total = make_windows(a.v, pos, w, lane, &ws);
 
-    uint64_t L[KR];
-#pragma unroll
-    for (int i = 0; i < KR; i++) L[i] = kNone;
-    uint32_t nbuf = 0;          // BIGK: keys in s_buf
-    uint64_t tau = kNone;       // BIGK: k-th distinct key so far
-    if constexpr (BIGK) {
-        for (uint32_t i = lane; i < k; i += 64) s_run[i] = kNone;
-    }
-
-    auto flush = [&]() {
-        // sort the buffer, merge it into the running list, tighten tau
-        __syncthreads();
-        for (uint32_t i = nbuf + lane; i < (uint32_t)kBuf; i += 64) s_buf[i] = kNone;
-        __syncthreads();
-        for (uint32_t size = 2; size <= (uint32_t)kBuf; size <<= 1) {
-            for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-                for (uint32_t i = lane; i < (uint32_t)kBuf / 2; i += 64) {
-                    const uint32_t lo = 2 * stride * (i / stride) + (i % stride);
-                    const uint32_t hi = lo + stride;
-                    const bool up = (lo & size) == 0;
-                    const uint64_t x0 = s_buf[lo], x1 = s_buf[hi];
-                    if ((x0 > x1) == up) {
-                        s_buf[lo] = x1;
-                        s_buf[hi] = x0;
-                    }
-                }
-                __syncthreads();
-            }
-        }
-        if (lane == 0) {
-            merge_distinct(s_run, k, s_buf, nbuf, k, s_out);
-            for (uint32_t i = 0; i < k; i++) s_run[i] = s_out[i];
-        }
-        __syncthreads();
-        tau = s_run[k - 1];
-        nbuf = 0;
-    };
-
-    // ---- 3-5. stream the window slots -------------------------------------
-    for (uint64_t base = 0; base < total; base += 64 * G) {
-        // ids of the G*64 slots: lane l loads slot base + 64 g + l (coalesced)
-        uint32_t myid[G];
-#pragma unroll
-        for (int g = 0; g < G; g++) {
-            const uint64_t s = base + 64 * g + lane;
-            myid[g] = 0;
-            if (s < total) {
-                int c = 0;
-#pragma unroll
-                for (int j = 1; j < kMaxCurves; j++) c += s >= off[j] ? 1 : 0;
-                myid[g] = s_base[c][s - s_off[c]];
-            }
-        }
-        // rows: in step t of group g, lanes 8r..8r+7 read row (g, 8t + r)
-        uint4 x[8 * G];
-#pragma unroll
-        for (int g = 0; g < G; g++)
-#pragma unroll
-            for (int t = 0; t < 8; t++) {
-                const uint32_t rid = __shfl(myid[g], 8 * t + (lane >> 3), 64);
-                const uint64_t s = base + 64 * g + 8 * t + (lane >> 3);
-                x[8 * g + t] = s < total
-                    ? *reinterpret_cast<const uint4 *>(a.v.db + (uint64_t)rid * kDim + 16 * part)
-                    : make_uint4(0, 0, 0, 0);
-            }
-#pragma unroll
-        for (int g = 0; g < G; g++) {
-            uint32_t mine = 0;
-#pragma unroll
-            for (int t = 0; t < 8; t++) {
-                uint32_t d = sqdist16(qv, qq, x[8 * g + t]);
-                d += __shfl_xor(d, 1, 64);
-                d += __shfl_xor(d, 2, 64);
-                d += __shfl_xor(d, 4, 64);
-                if (part == t) mine = d;
-            }
-            const uint32_t mid = __shfl(myid[g], 8 * part + (lane >> 3), 64);
-            // this lane now holds slot base + 64 g + 8 part + (lane >> 3)
-            const uint64_t s = base + 64 * g + 8 * part + (lane >> 3);
-            const uint64_t key = s < total ? (((uint64_t)mine << 32) | mid) : kNone;
-            if constexpr (!BIGK) {
-                insert_distinct<KR>(L, key);
-            } else {
-                const bool pass = key < tau;
-                const uint64_t m = __ballot(pass);
-                if (pass) s_buf[nbuf + lanes_below64(m)] = key;
-                nbuf += (uint32_t)__popcll(m);
-                if (nbuf > (uint32_t)(kBuf - 64)) flush();
-            }
-        }
-    }
-
-    if constexpr (!BIGK) {
-        uint64_t mykey = kNone;
-        for (uint32_t j = 0; j < k; j++) {
-            const uint64_t m = wave_min_u64(L[0]);
-            if ((uint32_t)lane == j) mykey = m;
-            if (m != kNone && L[0] == m) {   // every lane holding m pops it
-#pragma unroll
-                for (int i = 0; i < KR - 1; i++) L[i] = L[i + 1];
-                L[KR - 1] = kNone;
-            }
-        }
-        if ((uint32_t)lane < k) {
-            a.out_ids[(uint64_t)q * k + lane] = (uint32_t)mykey;
-            a.out_dists[(uint64_t)q * k + lane] = (uint32_t)(mykey >> 32);
-        }
-    } else {
-        if (nbuf) flush();
-        for (uint32_t i = lane; i < k; i += 64) {
-            const uint64_t key = s_run[i];
-            a.out_ids[(uint64_t)q * k + i] = (uint32_t)key;
-            a.out_dists[(uint64_t)q * k + i] = (uint32_t)(key >> 32);
-        }
-    }
+    WaveTopK<KR> top;
+    top.init(a.k, tks, lane);
+    stream_slots<G>(a.v.db, &ws, 0, total, qv, qq, lane, top);
+    const uint64_t o = (uint64_t)q * a.k;
+    top.finish(lane, [&](uint32_t j, uint64_t key) {
+        a.out_ids[o + j] = (uint32_t)key;
+        a.out_dists[o + j] = (uint32_t)(key >> 32);
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -401,10 +208,10 @@ static uint32_t ceil_log2(uint64_t x)
     return l;
 }
 
-template <int KR, int G, bool BIGK>
+template <int KR, int G>
 static hc_status launch_stream(const SearchArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_stream<KR, G, BIGK>), dim3(a.nq), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_stream<KR, G>), dim3(a.nq), dim3(64), 0, st, a);
     return last_hip();
 }
 
@@ -413,11 +220,11 @@ static hc_status launch_stream(const SearchArgs &a, hipStream_t st)
 template <int G>
 static hc_status launch_search_g(const SearchArgs &a, hipStream_t st)
 {
-    if (a.k == 1) return launch_stream<1, G, false>(a, st);
-    if (a.k <= 4) return launch_stream<4, G, false>(a, st);
-    if (a.k <= 10) return launch_stream<10, G, false>(a, st);
-    if (a.k <= (uint32_t)kKR) return launch_stream<kKR, G, false>(a, st);
-    return launch_stream<1, G, true>(a, st);
+    if (a.k == 1) return launch_stream<1, G>(a, st);
+    if (a.k <= 4) return launch_stream<4, G>(a, st);
+    if (a.k <= 10) return launch_stream<10, G>(a, st);
+    if (a.k <= (uint32_t)kKR) return launch_stream<kKR, G>(a, st);
+    return launch_stream<0, G>(a, st);
 }
 
 static hc_status launch_search(const SearchArgs &a, uint64_t w_hint, hipStream_t st)

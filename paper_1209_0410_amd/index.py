@@ -99,6 +99,12 @@ class Index:
             self._scratch = _empty_bytes(sz.value, self.db.device)
         return self._scratch
 
+    def new_scratch(self, nq):
+        """A scratch buffer of its own (for concurrent streams)."""
+        sz = ct.c_size_t()
+        capi.call("hc_search_scratch_bytes", self.handle, nq, ct.byref(sz))
+        return _empty_bytes(sz.value, self.db.device)
+
     def curve(self, c):
         """(keys int64 (n, 2) of {hi, lo}, ids int32 (n,)) views of curve c's list."""
         kp, ip = ct.c_void_p(), ct.c_void_p()
@@ -142,6 +148,31 @@ class Index:
                   int(w or 0), wp, _ptr(ids), _ptr(dists), _ptr(scratch), scratch.numel(),
                   _stream())
         return ids, dists
+
+    def uneven_scratch(self, nq, k_stride, cfg=None):
+        sz = ct.c_size_t()
+        capi.call("hc_uneven_scratch_bytes", self.handle, nq, k_stride,
+                  ct.byref(cfg) if cfg is not None else None, ct.byref(sz))
+        return _empty_bytes(sz.value, self.db.device)
+
+    def search_uneven(self, queries, w=0, k=10, w_per_query=None, k_per_query=None,
+                      k_stride=None, cfg=None, out=None, scratch=None):
+        """Per-query w and k in one persistent launch: (ids, dists) int32 (nq, k_stride),
+        row q holding k_q results then 0xFFFFFFFF."""
+        _check_rows(queries, "queries")
+        nq = queries.shape[0]
+        if k_stride is None:
+            k_stride = int(k_per_query.max().item()) if k_per_query is not None else int(k)
+        if out is None:
+            out = (torch.empty((nq, k_stride), dtype=torch.int32, device=queries.device),
+                   torch.empty((nq, k_stride), dtype=torch.int32, device=queries.device))
+        sc = scratch if scratch is not None else self.uneven_scratch(nq, k_stride, cfg)
+        capi.call("hc_search_uneven", self.handle, _ptr(queries), nq, int(w),
+                  _ptr(w_per_query) if w_per_query is not None else None, int(k),
+                  _ptr(k_per_query) if k_per_query is not None else None, k_stride,
+                  _ptr(out[0]), _ptr(out[1]), _ptr(sc), sc.numel(),
+                  ct.byref(cfg) if cfg is not None else None, _stream())
+        return out
 
     def positions(self, queries):
         _check_rows(queries, "queries")

@@ -1,0 +1,209 @@
+"""Continuous-batching request loop over a resident index (one GPU).
+
+Requests (a query vector and its k) arrive over time.  The loop admits every
+request that has arrived into the next batch whenever an in-flight slot is
+free and the batch's device memory fits the HBM budget; each batch runs on its
+own HIP stream (copy in, per-query w, the uneven search, copy out), so batches
+overlap on the device while new requests keep arriving.  This is the online
+setting of the paper's Sec. 6 (tasks arrive continuously; the group size is
+decided at run time), with slots on streams in place of its CPU/GPU buffers.
+
+The arrival process is seeded: Poisson with a rate that varies sinusoidally,
+drawn by thinning (Lewis & Shedler).
+"""
+import collections
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import capi, learned
+
+
+def sinusoidal_arrivals(duration_s, lo_qps, hi_qps, period_s, seed):
+    """Arrival times (s) of a Poisson process with rate
+    mid - amp * cos(2 pi t / period), mid = (hi + lo) / 2, amp = (hi - lo) / 2."""
+    rng = np.random.default_rng(seed)
+    mid, amp = 0.5 * (hi_qps + lo_qps), 0.5 * (hi_qps - lo_qps)
+    lam_max = hi_qps
+    n = rng.poisson(lam_max * duration_s)
+    t = np.sort(rng.uniform(0.0, duration_s, size=n))
+    rate = mid - amp * np.cos(2 * math.pi * t / period_s)
+    keep = rng.uniform(0.0, lam_max, size=n) < rate
+    return t[keep]
+
+
+class HbmBudget:
+    """Device bytes the in-flight batches may hold (admission control)."""
+
+    def __init__(self, budget_bytes=None, reserve_bytes=2 << 30):
+        if budget_bytes is None:
+            free, _ = torch.cuda.mem_get_info()
+            budget_bytes = max(0, free - reserve_bytes)
+        self.budget = int(budget_bytes)
+        self.used = 0
+        self.peak = 0
+        self.refused = 0
+
+    def take(self, nbytes):
+        if self.used + nbytes > self.budget:
+            return False
+        self.used += nbytes
+        self.peak = max(self.peak, self.used)
+        return True
+
+    def give(self, nbytes):
+        self.used -= nbytes
+
+
+class _Slot:
+    def __init__(self, ix, cap, k_stride, dev, cfg):
+        self.stream = torch.cuda.Stream(device=dev)
+        self.q = torch.empty((cap, 128), dtype=torch.uint8, device=dev)
+        self.k = torch.empty(cap, dtype=torch.int32, device=dev)
+        self.w = torch.empty(cap, dtype=torch.int32, device=dev)
+        self.feat = torch.empty((cap, learned.FEATURES), dtype=torch.float32, device=dev)
+        self.ids = torch.empty((cap, k_stride), dtype=torch.int32, device=dev)
+        self.dists = torch.empty((cap, k_stride), dtype=torch.int32, device=dev)
+        self.scratch = ix.uneven_scratch(cap, k_stride, cfg)
+        self.fscratch = ix.new_scratch(cap)
+        self.host_ids = torch.empty((cap, k_stride), dtype=torch.int32).pin_memory()
+        self.host_dists = torch.empty((cap, k_stride), dtype=torch.int32).pin_memory()
+        self.done = torch.cuda.Event()
+        self.busy = False
+
+
+def batch_bytes(nq, k_stride, curves=8, max_split=32):
+    """Device bytes one batch of nq requests needs beyond the resident index."""
+    return nq * (128 + 8 + 4 * learned.FEATURES + 8 * k_stride +
+                 16 * curves + 4 * curves + 4 + 8 * max_split * k_stride)
+
+
+class Server:
+    """Admits arriving requests into batches on `slots` streams."""
+
+    def __init__(self, ix, model=None, w_fixed=64, k_stride=100, max_batch=4096, slots=3,
+                 budget=None, cfg=None, w_fallback=None):
+        self.ix = ix
+        self.model = model
+        self.w_fixed = int(w_fixed)
+        self.w_fallback = int(w_fallback if w_fallback is not None else w_fixed)
+        self.k_stride = int(k_stride)
+        self.max_batch = int(max_batch)
+        self.cfg = cfg
+        dev = ix.db.device
+        self.slots = [_Slot(ix, self.max_batch, self.k_stride, dev, cfg) for _ in range(slots)]
+        self.budget = budget if budget is not None else HbmBudget()
+
+    def _launch(self, slot, hq, hk, lo, hi):
+        nq = hi - lo
+        with torch.cuda.stream(slot.stream):
+            slot.q[:nq].copy_(hq[lo:hi], non_blocking=True)
+            slot.k[:nq].copy_(hk[lo:hi], non_blocking=True)
+            q = slot.q[:nq]
+            if self.model is not None:
+                kmax = int(self.k_stride)
+                capi.call("hc_features", self.ix.handle, ctp(q), nq, kmax, ctp(slot.k),
+                          ctp(slot.feat), ctp(slot.fscratch), slot.fscratch.numel(),
+                          stream_of(slot.stream))
+                capi.call("hc_mlp_infer", ctp(self.model.bf16), ctp(self.model.norm),
+                          ctp(slot.feat), nq, float(self.model.delta), self.model.w_min,
+                          self.model.w_max, self.w_fallback, ctp(slot.w), None,
+                          stream_of(slot.stream))
+                wp = slot.w[:nq]
+            else:
+                wp = None
+            capi.call("hc_search_uneven", self.ix.handle, ctp(q), nq, self.w_fixed,
+                      ctp(wp) if wp is not None else None, 1, ctp(slot.k), self.k_stride,
+                      ctp(slot.ids), ctp(slot.dists), ctp(slot.scratch), slot.scratch.numel(),
+                      _cfgp(self.cfg), stream_of(slot.stream))
+            slot.host_ids[:nq].copy_(slot.ids[:nq], non_blocking=True)
+            slot.host_dists[:nq].copy_(slot.dists[:nq], non_blocking=True)
+            slot.done.record(slot.stream)
+        slot.busy = True
+
+    def run(self, arrivals, queries, ks, keep_results=True, realtime=True, log=None):
+        """Serves requests i (arrival time arrivals[i] s, row queries[i], k ks[i]).
+        Returns per-request latency (s) and, if asked, the results."""
+        R = len(arrivals)
+        hq = torch.from_numpy(queries).pin_memory()
+        hk = torch.from_numpy(np.ascontiguousarray(ks, np.uint32).view(np.int32)).pin_memory()
+        done_at = np.zeros(R)
+        res_ids = np.zeros((R, self.k_stride), np.uint32) if keep_results else None
+        res_d = np.zeros((R, self.k_stride), np.uint32) if keep_results else None
+        inflight = collections.deque()      # (slot, lo, hi, bytes)
+        nxt = 0
+        batches = 0
+        sizes = []
+        t0 = time.perf_counter()
+        clock = (lambda: time.perf_counter() - t0) if realtime else None
+        while nxt < R or inflight:
+            now = clock() if realtime else math.inf
+            # retire finished batches (oldest first; each slot records one event)
+            for _ in range(len(inflight)):
+                slot, lo, hi, nb = inflight[0]
+                if not slot.done.query():
+                    inflight.rotate(-1)
+                    continue
+                inflight.popleft()
+                t_done = clock() if realtime else 0.0
+                done_at[lo:hi] = t_done
+                if keep_results:
+                    res_ids[lo:hi] = slot.host_ids[:hi - lo].numpy().view(np.uint32)
+                    res_d[lo:hi] = slot.host_dists[:hi - lo].numpy().view(np.uint32)
+                slot.busy = False
+                self.budget.give(nb)
+            # admit what has arrived into a free slot, as much as the budget allows
+            ready_end = nxt
+            while ready_end < R and arrivals[ready_end] <= now and ready_end - nxt < self.max_batch:
+                ready_end += 1
+            free = [s for s in self.slots if not s.busy]
+            if ready_end > nxt and free:
+                per = batch_bytes(1, self.k_stride)
+                fit = (self.budget.budget - self.budget.used) // per
+                if fit < 1 and not inflight:
+                    raise RuntimeError("HBM budget is below one request's device memory")
+                end = min(ready_end, nxt + int(fit))
+                if end > nxt and self.budget.take(batch_bytes(end - nxt, self.k_stride)):
+                    nb = batch_bytes(end - nxt, self.k_stride)
+                    self._launch(free[0], hq, hk, nxt, end)
+                    inflight.append((free[0], nxt, end, nb))
+                    sizes.append(end - nxt)
+                    batches += 1
+                    nxt = end
+                    continue
+                self.budget.refused += 1
+            if not realtime and not free and inflight:
+                inflight[0][0].done.synchronize()
+            elif realtime and nxt < R and ready_end == nxt and not inflight:
+                time.sleep(max(0.0, min(arrivals[nxt] - now, 0.001)))
+        torch.cuda.synchronize()
+        lat = done_at - np.asarray(arrivals) if realtime else None
+        stats = {"requests": R, "batches": batches,
+                 "mean_batch": float(np.mean(sizes)) if sizes else 0.0,
+                 "max_batch": int(max(sizes)) if sizes else 0,
+                 "hbm_budget": self.budget.budget, "hbm_peak": self.budget.peak,
+                 "admission_waits": self.budget.refused}
+        if realtime:
+            stats.update({"p50_ms": float(np.percentile(lat, 50) * 1e3),
+                          "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                          "mean_ms": float(lat.mean() * 1e3),
+                          "span_s": float(done_at.max()),
+                          "sustained_qps": R / float(done_at.max())})
+        return stats, (res_ids, res_d)
+
+
+def ctp(t):
+    import ctypes as ct
+    return ct.c_void_p(t.data_ptr())
+
+
+def stream_of(s):
+    import ctypes as ct
+    return ct.c_void_p(s.cuda_stream)
+
+
+def _cfgp(cfg):
+    import ctypes as ct
+    return ct.byref(cfg) if cfg is not None else None

@@ -1,0 +1,104 @@
+"""The continuous-batching request loop: every request's result is the same
+as when it is searched alone (integer results, bit-exact), under a
+fluctuating arrival rate, with and without a tight HBM budget, with a learned
+w per request."""
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+def u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+@pytest.fixture(scope="module")
+def env(oracle):
+    import torch
+    from paper_1209_0410_amd import datagen
+    from paper_1209_0410_amd.index import Index
+    db = datagen.make_db(50_000)
+    gix = Index(torch.from_numpy(db).cuda())
+    R = 4000
+    q = datagen.make_queries(R, seed=21)
+    ks = np.random.default_rng(22).choice([1, 10, 100], size=R).astype(np.uint32)
+    return dict(db=db, gix=gix, q=q, ks=ks, oix=oracle.Index(db))
+
+
+def alone(gix, q, ks, w, k_stride=100):
+    """Each request searched by itself."""
+    import torch
+    ids = np.zeros((len(q), k_stride), np.uint32)
+    d = np.zeros((len(q), k_stride), np.uint32)
+    for i in range(len(q)):
+        gi, gd = gix.search_uneven(torch.from_numpy(q[i:i + 1]).cuda(), w=int(w[i]),
+                                   k=int(ks[i]), k_stride=k_stride)
+        ids[i], d[i] = u32(gi)[0], u32(gd)[0]
+    return ids, d
+
+
+def test_results_equal_alone_and_in_the_mix(env):
+    from paper_1209_0410_amd.serve import Server, sinusoidal_arrivals
+    arr = sinusoidal_arrivals(0.4, 2000, 20000, 0.4, seed=23)
+    R = min(len(arr), len(env["q"]))
+    arr = arr[:R]
+    srv = Server(env["gix"], w_fixed=24, k_stride=100, max_batch=512, slots=3)
+    stats, (ids, d) = srv.run(arr, env["q"][:R], env["ks"][:R])
+    assert stats["requests"] == R and stats["batches"] > 1
+    w = np.full(R, 24)
+    sel = np.arange(0, R, 7)
+    ai, ad = alone(env["gix"], env["q"][sel], env["ks"][sel], w[sel])
+    assert (ids[sel] == ai).all() and (d[sel] == ad).all()
+    # and against the oracle, per k
+    for kk in (1, 10, 100):
+        m = sel[env["ks"][sel] == kk]
+        rid, rd = env["oix"].search(env["q"][m], int(kk), 24)
+        assert (ids[m, :kk] == rid).all() and (d[m, :kk] == rd).all()
+    assert np.isfinite(stats["p99_ms"]) and stats["p99_ms"] >= stats["p50_ms"]
+
+
+def test_tight_hbm_budget_limits_batches(env):
+    from paper_1209_0410_amd.serve import HbmBudget, Server, batch_bytes
+    R = 1500
+    arr = np.zeros(R)                       # everything arrives at once
+    budget = HbmBudget(batch_bytes(200, 100))
+    srv = Server(env["gix"], w_fixed=16, k_stride=100, max_batch=1024, slots=3, budget=budget)
+    stats, (ids, d) = srv.run(arr, env["q"][:R], env["ks"][:R])
+    assert stats["max_batch"] <= 200 and budget.peak <= budget.budget
+    assert stats["admission_waits"] > 0
+    srv2 = Server(env["gix"], w_fixed=16, k_stride=100, max_batch=1024, slots=1)
+    _, (ids2, d2) = srv2.run(arr, env["q"][:R], env["ks"][:R])
+    assert (ids == ids2).all() and (d == d2).all()
+
+
+def test_budget_below_one_request_is_an_error(env):
+    from paper_1209_0410_amd.serve import HbmBudget, Server
+    srv = Server(env["gix"], w_fixed=16, k_stride=100, max_batch=64, slots=1,
+                 budget=HbmBudget(1000))
+    with pytest.raises(RuntimeError):
+        srv.run(np.zeros(10), env["q"][:10], env["ks"][:10])
+
+
+def test_learned_w_per_request_in_the_mix(env):
+    import torch
+    from paper_1209_0410_amd import learned
+    from paper_1209_0410_amd.serve import Server, sinusoidal_arrivals
+    model = learned.WModel(torch.device("cuda:0"), seed=5, w_min=8, w_max=256)
+    feats = learned.features(env["gix"], torch.from_numpy(env["q"]).cuda(), 10)
+    model.set_norm(feats)
+    model.delta = 5.0
+    arr = sinusoidal_arrivals(0.3, 2000, 15000, 0.3, seed=24)
+    R = min(len(arr), 1500)
+    srv = Server(env["gix"], model=model, w_fixed=32, k_stride=100, max_batch=256, slots=2)
+    stats, (ids, d) = srv.run(arr[:R], env["q"][:R], env["ks"][:R])
+    # the w each request got depends on its own features only
+    gq = torch.from_numpy(env["q"][:R]).cuda()
+    gk = torch.from_numpy(env["ks"][:R].view(np.int32)).cuda()
+    f = learned.features(env["gix"], gq, 0, gk)
+    w = u32(model.windows(f, w_fallback=32))
+    sel = np.arange(0, R, 9)
+    ai, ad = alone(env["gix"], env["q"][sel], env["ks"][sel], w[sel])
+    assert (ids[sel] == ai).all() and (d[sel] == ad).all()
