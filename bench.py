@@ -30,6 +30,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# dot4 peak of the vector ALUs: 256 CUs x 64 lanes x 4 int8 MACs per lane per
+# cycle x 2 ops per MAC x 2.4 GHz
+ALU_PEAK_TOPS = 256 * 64 * 4 * 2 * 2.4e9 / 1e12
 TARGET = 0.90
 CALIB_TARGET = 0.905    # margin for the sampling error of the evaluation recall
 
@@ -158,12 +161,14 @@ def main():
         slots = window_slots(w)
         ab = alg_bytes(slots, uni)
         rows.append(dict(w=w, step_ms=step_ms, kernel_ms=kern_ms, qps=a.nq / step_ms * 1e3,
+                         path=path_name(ix.path(a.nq, k, w, sc.numel())),
                          recall=rec, union_per_query=uni / a.nq, alg_bytes=ab,
                          alg_GBs=ab / (kern_ms * 1e-3) / 1e9,
                          frac=ab / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS))
         r = rows[-1]
-        log(f"fixed w={w}: {step_ms:.3f} ms/step, {r['qps']:.3e} q/s, recall {rec:.4f}, "
-            f"union/q {r['union_per_query']:.0f}, {r['alg_GBs']:.0f} GB/s ({r['frac']:.1%})")
+        log(f"fixed w={w} ({r['path']}): {step_ms:.3f} ms/step, {r['qps']:.3e} q/s, "
+            f"recall {rec:.4f}, union/q {r['union_per_query']:.0f}, {r['alg_GBs']:.0f} GB/s "
+            f"({r['frac']:.1%})")
 
     # ---- calibration at recall >= 0.90 ------------------------------------------
     cq = datagen.make_queries(a.calib_q, seed=datagen.SEED_CALIB)
@@ -181,7 +186,8 @@ def main():
     f_ab = alg_bytes(window_slots(w_fix), f_uni)
     fixed = dict(w=w_fix, step_ms=fs, kernel_ms=fk, wall_ms=fwall, qps=a.nq / fs * 1e3,
                  recall=f_rec, union_per_query=f_uni / a.nq, alg_bytes=f_ab,
-                 alg_GBs=f_ab / (fk * 1e-3) / 1e9)
+                 alg_GBs=f_ab / (fk * 1e-3) / 1e9, path=path_name(ix.path(a.nq, k, w_fix, sc.numel())),
+                 alg_TOPs=2 * 128 * f_uni / (fk * 1e-3) / 1e12)
     log(f"fixed w={w_fix}: {fs:.3f} ms/step, {fixed['qps']:.3e} q/s, recall {f_rec:.4f}")
 
     learned_row = None
@@ -249,13 +255,9 @@ def main():
         "build_s": build_s,
         "sweep": rows,
         "uneven": uneven,
-        "roofline": {"bound": "hbm", "achieved": head["alg_GBs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": head["alg_GBs"] / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_stream (hc_search_encoded)",
-                     "kernel_ms": head["kernel_ms"],
-                     "alg_bytes_per_launch": head["alg_bytes"]},
+        "roofline": roofline(head),
     }
-    if head is fixed:
+    if head is fixed and head["path"] == "gather":
         tb, tsrc = counted_traffic(a.n, a.nq, k, w_fix)
         if tb is not None:
             result["roofline"]["traffic"] = tb
@@ -310,6 +312,8 @@ def run_learned(a, ix, rank, gdb, gq, gcq, ctruth, out, sc, timed, recall_of, al
     uni = int(learned.union_sizes(ix, rank, gq, 0, wq).cpu().numpy().view(np.uint32).sum())
     ab = alg_bytes(window_slots(wv.astype(np.int64)), uni)
     row = dict(step_ms=ls, kernel_ms=lk, wall_ms=lwall, qps=a.nq / ls * 1e3, recall=rec,
+               path=path_name(ix.path(a.nq, k, model.w_hint, sc.numel())),
+               alg_TOPs=2 * 128 * uni / (lk * 1e-3) / 1e12,
                delta=delta, mean_w=float(wv.mean()),
                w_pct=np.percentile(wv, [10, 50, 90, 99]).tolist(),
                union_per_query=uni / a.nq, alg_bytes=ab, alg_GBs=ab / (lk * 1e-3) / 1e9,
@@ -319,6 +323,27 @@ def run_learned(a, ix, rank, gdb, gq, gcq, ctruth, out, sc, timed, recall_of, al
         f"{row['mean_w']:.0f}")
     row["_model"] = model
     return row
+
+
+def path_name(p):
+    return {1: "gather", 2: "band"}[p]
+
+
+def roofline(head):
+    """Roofline of the search call (hc_search_encoded): HBM-bound on the gather
+    path (window ids + distinct rows + results per launch), ALU-bound on the
+    banded path (2 x 128 int8 MAC-ops per distinct candidate per launch)."""
+    if head["path"] == "gather":
+        return {"bound": "hbm", "achieved": head["alg_GBs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": head["alg_GBs"] / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "k_stream (hc_search_encoded, gather path)",
+                "kernel_ms": head["kernel_ms"], "alg_bytes_per_launch": head["alg_bytes"]}
+    return {"bound": "alu", "achieved": head["alg_TOPs"], "peak": ALU_PEAK_TOPS,
+            "unit": "TOP/s", "frac": head["alg_TOPs"] / ALU_PEAK_TOPS, "traffic": None,
+            "kernel": "k_band + place/sort/merge (hc_search_encoded, banded path)",
+            "kernel_ms": head["kernel_ms"],
+            "alg_ops_per_launch": head["alg_TOPs"] * 1e12 * head["kernel_ms"] * 1e-3,
+            "hbm_alg_GBs": head["alg_GBs"]}
 
 
 def counted_traffic(n, nq, k, w):
@@ -407,7 +432,7 @@ def _learned_split(ix, model, gq, k, out, sc, feats_b, wq, ev, st):
     capi.call("hc_mlp_infer", _ptr(model.bf16), _ptr(model.norm), _ptr(feats_b), nq,
               float(model.delta), model.w_min, model.w_max, 64, _ptr(wq), None, _stream())
     ev[1].record(st)
-    ix.search_encoded(gq, k, 0, out, sc, w_per_query=wq)
+    ix.search_encoded(gq, k, model.w_hint, out, sc, w_per_query=wq)
 
 
 def check_truth(db, q, truth, k, m=16):

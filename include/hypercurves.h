@@ -122,8 +122,10 @@ hc_status hc_index_info(const hc_index *idx, uint64_t *n, uint32_t *curves);
 /* Search (Alg. 2)                                                         */
 /* ---------------------------------------------------------------------- */
 
-/* Scratch bytes hc_search_batch needs for nq queries (also valid for
- * hc_positions and hc_candidates). */
+/* Scratch bytes hc_search_batch needs for nq queries on either path (also
+ * valid for hc_positions, hc_candidates and the learned-depth entry points).
+ * A smaller buffer of at least nq * curves * 16 bytes restricts the search to
+ * the gather path. */
 hc_status hc_search_scratch_bytes(const hc_index *idx, uint32_t nq, size_t *bytes);
 
 /* Alg. 2 for a batch of queries (d_queries: nq x 128 uint8).  Per query and
@@ -154,6 +156,26 @@ hc_status hc_search_encoded(const hc_index *idx, const uint8_t *d_queries, uint3
                             uint32_t k, uint32_t w_fixed, const uint32_t *d_w,
                             uint32_t *d_out_ids, uint32_t *d_out_dists,
                             void *d_scratch, size_t scratch_bytes, hc_stream stream);
+
+/* Execution paths of the search; both give identical results.
+ *  HC_PATH_GATHER: one wavefront per query gathers its candidates' rows.
+ *  HC_PATH_BAND:   per curve, the batch ordered by place in the list; one
+ *                  wavefront per 64 neighbouring queries streams the union of
+ *                  their windows once and each lane keeps the entries inside
+ *                  its own window (for large batches with large windows, where
+ *                  one list entry lies in many windows).  k <= 16.
+ *  HC_PATH_AUTO:   banded when 2 w nq >= 10 n (w = w_fixed or the hint), k <= 16
+ *                  and the scratch holds hc_search_scratch_bytes; else gather.
+ * hc_search_encoded is hc_search_encoded_ex with HC_PATH_AUTO. */
+#define HC_PATH_AUTO 0u
+#define HC_PATH_GATHER 1u
+#define HC_PATH_BAND 2u
+hc_status hc_search_choose_path(const hc_index *idx, uint32_t nq, uint32_t k, uint32_t w,
+                                size_t scratch_bytes, uint32_t *path);
+hc_status hc_search_encoded_ex(const hc_index *idx, const uint8_t *d_queries, uint32_t nq,
+                               uint32_t k, uint32_t w_fixed, const uint32_t *d_w,
+                               uint32_t *d_out_ids, uint32_t *d_out_dists, void *d_scratch,
+                               size_t scratch_bytes, uint32_t path, hc_stream stream);
 
 /* Uneven batches: every query has its own w and its own k.  A query's window
  * slots (up to 16 w) are cut into work items of at most chunk_slots slots

@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(HERE, "libhypercurves.so")
 
 HC_OK, HC_ERR_INVALID, HC_ERR_SIZE, HC_ERR_HIP, HC_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 HC_K_MAX = 256
+HC_PATH_AUTO, HC_PATH_GATHER, HC_PATH_BAND = 0, 1, 2
 
 
 class HcError(RuntimeError):
@@ -49,6 +50,8 @@ SIGNATURES = {
     "hc_search_batch": [_vp, _vp, _u32, _u32, _u32, _vp, _vp, _vp, _vp, _sz, _vp],
     "hc_encode_queries": [_vp, _vp, _u32, _vp, _sz, _vp],
     "hc_search_encoded": [_vp, _vp, _u32, _u32, _u32, _vp, _vp, _vp, _vp, _sz, _vp],
+    "hc_search_choose_path": [_vp, _u32, _u32, _u32, _sz, ct.POINTER(_u32)],
+    "hc_search_encoded_ex": [_vp, _vp, _u32, _u32, _u32, _vp, _vp, _vp, _vp, _sz, _u32, _vp],
     "hc_encode_keys": [_pp, _vp, _u64, _vp, _vp],
     "hc_positions": [_vp, _vp, _u32, _vp, _vp, _sz, _vp],
     "hc_candidates": [_vp, _vp, _u32, _u32, _vp, _vp, _vp, _u32, _vp, _sz, _vp],

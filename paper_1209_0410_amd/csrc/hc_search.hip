@@ -32,6 +32,8 @@
 namespace hc {
 
 constexpr int kKR = 16;                 // longest register list (k <= 16)
+constexpr double kBandShare = 10.0;     // windows per list entry from which to band
+                                        // (MI355X, n = 1e7, nq = 1e5: break-even at w ~ 512)
 constexpr uint32_t kMaxSetSlots = 4096; // union capacity of the set kernel
 constexpr int kIdBatch = 16;            // set kernel: ids loaded before inserting
 
@@ -273,7 +275,9 @@ extern "C" {
 hc_status hc_search_scratch_bytes(const hc_index *idx, uint32_t nq, size_t *bytes)
 {
     if (!idx || !bytes) return HC_ERR_INVALID;
-    *bytes = align256(sizeof(Key) * (size_t)std::max<uint32_t>(nq, 1) * idx->v.curves);
+    const uint32_t m = std::max<uint32_t>(nq, 1);
+    *bytes = std::max(align256(sizeof(Key) * (size_t)m * idx->v.curves),
+                      band_scratch_bytes(idx->v.curves, idx->v.n, m));
     return HC_OK;
 }
 
@@ -286,23 +290,50 @@ hc_status hc_encode_queries(const hc_index *idx, const uint8_t *d_queries, uint3
     return encode_rows(idx->v, d_queries, nq, (Key *)d_scratch, (hipStream_t)stream);
 }
 
-hc_status hc_search_encoded(const hc_index *idx, const uint8_t *d_queries, uint32_t nq,
-                            uint32_t k, uint32_t w_fixed, const uint32_t *d_w,
-                            uint32_t *d_out_ids, uint32_t *d_out_dists, void *d_scratch,
-                            size_t scratch_bytes, hc_stream stream)
+hc_status hc_search_encoded_ex(const hc_index *idx, const uint8_t *d_queries, uint32_t nq,
+                               uint32_t k, uint32_t w_fixed, const uint32_t *d_w,
+                               uint32_t *d_out_ids, uint32_t *d_out_dists, void *d_scratch,
+                               size_t scratch_bytes, uint32_t path, hc_stream stream)
 {
-    if (k < 1 || k > HC_K_MAX || !d_out_ids || !d_out_dists) return HC_ERR_INVALID;
+    if (k < 1 || k > HC_K_MAX || !d_out_ids || !d_out_dists || path > HC_PATH_BAND)
+        return HC_ERR_INVALID;
     if (nq == 0) return HC_OK;
     hc_status st = check_common(idx, d_queries, d_scratch, scratch_bytes, nq);
     if (st != HC_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const uint64_t hint = d_w ? (w_fixed ? w_fixed : 64) : w_fixed;
+    if (path == HC_PATH_AUTO) hc_search_choose_path(idx, nq, k, (uint32_t)hint, scratch_bytes, &path);
+    if (path == HC_PATH_BAND)
+        return band_search(idx->v, d_queries, nq, k, w_fixed, d_w, d_out_ids, d_out_dists,
+                           d_scratch, scratch_bytes, s);
     SearchArgs a = base_args(idx, d_queries, nq, d_scratch);
     a.k = k;
     a.w_fixed = w_fixed;
     a.d_w = d_w;
     a.out_ids = d_out_ids;
     a.out_dists = d_out_dists;
-    const uint64_t hint = d_w ? (w_fixed ? w_fixed : 64) : w_fixed;
-    return launch_search(a, hint, (hipStream_t)stream);
+    return launch_search(a, hint, s);
+}
+
+hc_status hc_search_choose_path(const hc_index *idx, uint32_t nq, uint32_t k, uint32_t w,
+                                size_t scratch_bytes, uint32_t *path)
+{
+    if (!idx || !path) return HC_ERR_INVALID;
+    // banded when each list entry lies in enough windows of the batch (the rows
+    // it saves outweigh the entries its groups stream outside windows)
+    const bool shared = 2.0 * (double)w * nq >= kBandShare * (double)idx->v.n;
+    const bool fits = scratch_bytes >= band_scratch_bytes(idx->v.curves, idx->v.n, nq);
+    *path = (shared && fits && k >= 1 && k <= 16) ? HC_PATH_BAND : HC_PATH_GATHER;
+    return HC_OK;
+}
+
+hc_status hc_search_encoded(const hc_index *idx, const uint8_t *d_queries, uint32_t nq,
+                            uint32_t k, uint32_t w_fixed, const uint32_t *d_w,
+                            uint32_t *d_out_ids, uint32_t *d_out_dists, void *d_scratch,
+                            size_t scratch_bytes, hc_stream stream)
+{
+    return hc_search_encoded_ex(idx, d_queries, nq, k, w_fixed, d_w, d_out_ids, d_out_dists,
+                                d_scratch, scratch_bytes, HC_PATH_AUTO, stream);
 }
 
 hc_status hc_search_batch(const hc_index *idx, const uint8_t *d_queries, uint32_t nq,

@@ -99,6 +99,15 @@ class Index:
             self._scratch = _empty_bytes(sz.value, self.db.device)
         return self._scratch
 
+    def path(self, nq, k, w, scratch_bytes=None):
+        """Execution path hc_search_encoded takes (capi.HC_PATH_GATHER / _BAND)."""
+        if scratch_bytes is None:
+            scratch_bytes = self.scratch(nq).numel()
+        p = ct.c_uint32()
+        capi.call("hc_search_choose_path", self.handle, nq, k, int(w), scratch_bytes,
+                  ct.byref(p))
+        return p.value
+
     def new_scratch(self, nq):
         """A scratch buffer of its own (for concurrent streams)."""
         sz = ct.c_size_t()
@@ -117,7 +126,7 @@ class Index:
         return keys, ids
 
     # -- search ---------------------------------------------------------------
-    def search(self, queries, k, w=64, w_per_query=None, out=None, scratch=None):
+    def search(self, queries, k, w=64, w_per_query=None, out=None, scratch=None, path=0):
         """Alg. 2: (ids, dists) int32 tensors (nq, k); uint32 values, 0xFFFFFFFF = empty."""
         _check_rows(queries, "queries")
         nq = queries.shape[0]
@@ -131,8 +140,10 @@ class Index:
         if w_per_query is not None:
             assert w_per_query.dtype == torch.int32 and w_per_query.is_cuda
             wp = _ptr(w_per_query)
-        capi.call("hc_search_batch", self.handle, _ptr(queries), nq, k, int(w or 0), wp,
-                  _ptr(ids), _ptr(dists), _ptr(sc), sc.numel(), _stream())
+        capi.call("hc_encode_queries", self.handle, _ptr(queries), nq, _ptr(sc), sc.numel(),
+                  _stream())
+        capi.call("hc_search_encoded_ex", self.handle, _ptr(queries), nq, k, int(w or 0), wp,
+                  _ptr(ids), _ptr(dists), _ptr(sc), sc.numel(), int(path), _stream())
         return ids, dists
 
     def encode_queries(self, queries, scratch):
@@ -140,13 +151,14 @@ class Index:
         capi.call("hc_encode_queries", self.handle, _ptr(queries), queries.shape[0],
                   _ptr(scratch), scratch.numel(), _stream())
 
-    def search_encoded(self, queries, k, w, out, scratch, w_per_query=None):
-        """Second launch of search(): keys already in `scratch`."""
+    def search_encoded(self, queries, k, w, out, scratch, w_per_query=None, path=0):
+        """Second launch of search(): keys already in `scratch`.  path: 0 auto,
+        1 gather, 2 banded (capi.HC_PATH_*)."""
         ids, dists = out
         wp = _ptr(w_per_query) if w_per_query is not None else None
-        capi.call("hc_search_encoded", self.handle, _ptr(queries), queries.shape[0], k,
+        capi.call("hc_search_encoded_ex", self.handle, _ptr(queries), queries.shape[0], k,
                   int(w or 0), wp, _ptr(ids), _ptr(dists), _ptr(scratch), scratch.numel(),
-                  _stream())
+                  int(path), _stream())
         return ids, dists
 
     def uneven_scratch(self, nq, k_stride, cfg=None):

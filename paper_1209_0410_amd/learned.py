@@ -100,6 +100,7 @@ class WModel:
         self.norm = torch.cat([torch.zeros(FEATURES), torch.ones(FEATURES)]).to(device)
         self.delta = 0.0
         self.w_min, self.w_max = int(w_min), int(w_max)
+        self.w_hint = 64        # typical predicted w (sizes the search's execution path)
 
     def targets(self, label):
         """y = log2(clamp(label, w_min, w_max)) as float32 (host math on labels)."""
@@ -192,13 +193,15 @@ def calibrate_delta(ix: Index, model: WModel, queries, feats, truth, k, target=0
         return recall_at_k(ids.cpu().numpy().view(np.uint32), truth_np)
 
     if rec(hi) < target:
-        return hi, rec(hi)
-    for _ in range(iters):
-        mid = 0.5 * (lo + hi)
-        if rec(mid) >= target:
-            hi = mid
-        else:
-            lo = mid
+        lo = hi
+    else:
+        for _ in range(iters):
+            mid = 0.5 * (lo + hi)
+            if rec(mid) >= target:
+                hi = mid
+            else:
+                lo = mid
+    model.w_hint = max(1, int(model.windows(feats, hi).float().mean().item()))
     return hi, rec(hi)
 
 
@@ -217,7 +220,7 @@ def search_learned(ix: Index, model: WModel, queries, k, out, scratch, feats=Non
     capi.call("hc_mlp_infer", _ptr(model.bf16), _ptr(model.norm), _ptr(feats), nq,
               float(model.delta), model.w_min, model.w_max, int(w_fallback), _ptr(w), None,
               _stream())
-    ix.search_encoded(queries, k, 0, out, scratch, w_per_query=w)
+    ix.search_encoded(queries, k, model.w_hint, out, scratch, w_per_query=w)
     return out[0], out[1], w
 
 

@@ -160,3 +160,33 @@ def test_full_window_is_exact_knn(oracle, torch_mod):
     ids, d = gix.search(torch_mod.from_numpy(q).cuda(), 10, 3000)
     rid, rd = oracle.brute_force(db, q, 10)
     assert (u32(ids) == rid).all() and (u32(d) == rd).all()
+
+
+@pytest.mark.parametrize("k,w", [(10, 64), (1, 16), (10, 1), (16, 256), (4, 3000), (10, 0),
+                                 (7, 20_000)])
+def test_banded_path_bit_exact(c1, k, w):
+    """The banded execution (queries grouped by place in each list) gives the
+    gather search's results exactly."""
+    ids, d = c1["gix"].search(c1["gq"], k, w, path=2)
+    rid, rd = c1["oix"].search(c1["q"], k, w)
+    assert (u32(ids) == rid).all()
+    assert (u32(d) == rd).all()
+
+
+def test_banded_path_per_query_w(c1, torch_mod):
+    rng = np.random.default_rng(17)
+    w = rng.integers(0, 3000, size=1000).astype(np.uint32)
+    w[:3] = [0, 1, 90_000]
+    gw = torch_mod.from_numpy(w.view(np.int32)).cuda()
+    ids, d = c1["gix"].search(c1["gq"], 10, 512, w_per_query=gw, path=2)
+    rid, rd = c1["oix"].search(c1["q"], 10, w)
+    assert (u32(ids) == rid).all() and (u32(d) == rd).all()
+
+
+def test_auto_path_matches_both(c1):
+    for w in (8, 600):
+        a = c1["gix"].search(c1["gq"], 10, w, path=0)
+        g = c1["gix"].search(c1["gq"], 10, w, path=1)
+        b = c1["gix"].search(c1["gq"], 10, w, path=2)
+        for x, y in ((a, g), (g, b)):
+            assert (u32(x[0]) == u32(y[0])).all() and (u32(x[1]) == u32(y[1])).all()
