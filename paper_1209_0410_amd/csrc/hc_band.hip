@@ -7,17 +7,17 @@
 //  1. every query's place in every curve (the same descent as the search);
 //  2. per curve, the queries ordered by place (a counting sort on place
 //     buckets of 2^kBucketShift entries);
-//  3. a wavefront takes 64 consecutive queries of one curve and streams the
-//     union of their windows through LDS, 64 list entries at a time (ids and
-//     rows, x.x of each row); lane i keeps query i in registers and, for every
-//     entry inside its own window, computes the exact squared distance (dot4)
-//     and offers (distance, id) to its register top-k;
+//  3. a block takes 256 consecutive queries of one curve and streams the
+//     union of their windows through LDS, 128 list entries at a time; the
+//     distances of 32 queries against the tile's rows come from the matrix
+//     cores (below), and every entry inside a query's own window is offered,
+//     as (distance, id), to that query's register top-k;
 //  4. a merge takes each query's per-curve lists and keeps the k nearest
 //     distinct ids.
 // The candidates, distances and order are exactly those of the gather search
 // (Alg. 2): only the grouping of the work differs, so the results are
-// identical.  The per-pair cost is arithmetic (32 dot4 per pair); the rows
-// read from HBM drop by the number of queries sharing them.
+// identical.  The rows read from HBM drop by the number of queries sharing
+// them, and the per-pair arithmetic moves to the matrix cores.
 #include <string.h>
 
 #include <algorithm>
@@ -28,7 +28,6 @@
 namespace hc {
 
 constexpr int kBucketShift = 8;   // place buckets of 256 list entries
-constexpr int kBandRows = 64;     // list entries per LDS tile
 constexpr int kBandK = 16;        // longest list kept per query and curve
 
 struct BandArgs {
@@ -106,40 +105,105 @@ __global__ __launch_bounds__(256) void k_band_scatter(BandArgs a)
     a.order[slot] = q;
 }
 
-// grid (groups, curves): a wavefront for 64 queries that are neighbours in
-// curve c's order.  KR: list length (k <= KR).
+// ---------------------------------------------------------------------------
+// Distances on the matrix cores.  For a query q and a row x (bytes 0..255),
+//   sum (q - x)^2 = crow(x) + cq(q) + 2 * sum (127 - x_j)(q_j - 128)
+// with crow(x) = sum x_j (x_j - 256) and cq(q) = sum q_j^2 - 254 sum q_j + 128 * 2 * 127 * 128.
+// Both factors of the last sum are signed bytes (127 - x = x ^ 0x7F,
+// q - 128 = q ^ 0x80), so a 32 x 32 tile of those sums, rows by queries, is
+// one chain of four v_mfma_i32_32x32x32_i8 (K = 128).  Every term is an
+// exact integer: the distance is the same uint32 as the byte-wise one.
+//
+// Block: kMW wavefronts, 32 queries each, consecutive in curve c's order.  The
+// block streams the union of its queries' windows through LDS, kMRows entries
+// per tile (rows stored as 127 - x, 16-byte parts XOR-swizzled against bank
+// conflicts; crow and the id of each row beside them).  Lane l of a wavefront
+// holds query l % 32 as the B operand; the tile's rows are the A operand; the
+// result gives lane l the sums of its query with 16 of every 32 rows (the
+// rows 8g + 4h + j, h = l / 32).  So every query has two lanes, each keeping a
+// list of the nearest entries among its half of the rows; the halves are
+// merged at the end.  A sum becomes a candidate only if it is at most the
+// current k-th distance of either half (ties are settled by the id inside);
+// only then are the window test, the id and the insertion paid for.
+// ---------------------------------------------------------------------------
+constexpr int kMW = 8;              // wavefronts per block
+constexpr int kMQ = 32;             // queries per wavefront
+constexpr int kMRows = 128;         // list entries per LDS tile
+constexpr int kMThreads = 64 * kMW;
+constexpr int kMBlockQ = kMW * kMQ;
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+// 16-byte part c of tile row r; the XOR spreads the rows read together by
+// one ds_read_b128 over all banks.
+__device__ inline uint32_t mslot(uint32_t r, uint32_t c) { return r * 8 + (c ^ ((r >> 1) & 7)); }
+
+__device__ inline uint4 xor4(uint4 v, uint32_t m)
+{
+    return make_uint4(v.x ^ m, v.y ^ m, v.z ^ m, v.w ^ m);
+}
+
 template <int KR>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KR >= 10 ? 3 : 4)))
+__device__ inline int list_bound(const uint64_t (&L)[KR], int cq)
+{
+    return L[KR - 1] == kNone ? INT32_MAX : (int)(uint32_t)(L[KR - 1] >> 32) - cq;
+}
+
+// 1-D grid of groups * curves blocks.  Consecutive blocks go to different
+// XCDs; the mapping gives each XCD a run of neighbouring groups of one curve,
+// whose windows overlap, so that their rows meet in that XCD's L2.
+template <int KR>
+__global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(KR > 10 ? 3 : 4)))
 void k_band(BandArgs a)
 {
-    __shared__ uint4 tile[kBandRows * 8];
-    __shared__ uint32_t tile_xx[kBandRows];
-    __shared__ uint32_t tile_id[kBandRows];
-    const int lane = threadIdx.x;
-    const uint32_t c = blockIdx.y;
+    __shared__ uint4 tile[kMRows * 8];
+    __shared__ __align__(16) int tile_c[kMRows];
+    __shared__ uint32_t tile_id[kMRows];
+    __shared__ uint64_t wspan[2][kMW];
+
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int h = lane >> 5, qn = lane & 31;
     const uint32_t C = a.v.curves;
     const uint64_t n = a.v.n;
-    const uint64_t slot = (uint64_t)blockIdx.x * 64 + lane;
+    const uint32_t groups = (a.nq + kMBlockQ - 1) / kMBlockQ;
+    const uint32_t nb = groups * C;
+    const uint32_t per = nb / 8, rem = nb % 8, xcd = blockIdx.x % 8, idx = blockIdx.x / 8;
+    const uint32_t bb = xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+    const uint32_t grp = bb % groups, c = bb / groups;
+
+    // this lane's query: B operand (16-byte parts 2s + h), cq, window
+    const uint64_t slot = (uint64_t)grp * kMBlockQ + (uint64_t)wv * kMQ + qn;
     const bool live = slot < a.nq;
     const uint32_t q = live ? a.order[(uint64_t)c * a.nq + slot] : 0;
-
-    // this lane's query and window
-    uint4 qv[8];
-    uint32_t qq = 0;
+    v4i bq[4];
+    uint32_t qq = 0, sq = 0;
+    {
+        const uint4 *qrow = reinterpret_cast<const uint4 *>(a.queries + (uint64_t)q * kDim);
 #pragma unroll
-    for (int i = 0; i < 8; i++) {
-        qv[i] = live ? reinterpret_cast<const uint4 *>(a.queries + (uint64_t)q * kDim)[i]
-                     : make_uint4(0, 0, 0, 0);
-        qq = __builtin_amdgcn_udot4(qv[i].x, qv[i].x, qq, false);
-        qq = __builtin_amdgcn_udot4(qv[i].y, qv[i].y, qq, false);
-        qq = __builtin_amdgcn_udot4(qv[i].z, qv[i].z, qq, false);
-        qq = __builtin_amdgcn_udot4(qv[i].w, qv[i].w, qq, false);
+        for (int s = 0; s < 4; s++) {
+            const uint4 v = live ? qrow[2 * s + h] : make_uint4(0, 0, 0, 0);
+            qq = __builtin_amdgcn_udot4(v.x, v.x, qq, false);
+            qq = __builtin_amdgcn_udot4(v.y, v.y, qq, false);
+            qq = __builtin_amdgcn_udot4(v.z, v.z, qq, false);
+            qq = __builtin_amdgcn_udot4(v.w, v.w, qq, false);
+            sq = __builtin_amdgcn_udot4(v.x, 0x01010101u, sq, false);
+            sq = __builtin_amdgcn_udot4(v.y, 0x01010101u, sq, false);
+            sq = __builtin_amdgcn_udot4(v.z, 0x01010101u, sq, false);
+            sq = __builtin_amdgcn_udot4(v.w, 0x01010101u, sq, false);
+            const uint4 b = xor4(v, 0x80808080u);
+            bq[s] = v4i{(int)b.x, (int)b.y, (int)b.z, (int)b.w};
+        }
     }
+    qq += __shfl_xor(qq, 32, 64);
+    sq += __shfl_xor(sq, 32, 64);
+    const int cq = (int)(qq - 254u * sq + 4161536u);
     const uint64_t w = live ? (a.d_w ? a.d_w[q] : a.w_fixed) : 0;
     const uint64_t p = live ? a.pos[(uint64_t)q * C + c] : 0;
     const uint64_t lo = live ? (p > w ? p - w : 0) : ~0ull;
     const uint64_t hi = live ? (p + w < n ? p + w : n) : 0;
-    // union of the group's windows
+
+    // unions of the wavefront's and of the block's windows
     uint64_t u0 = lo, u1 = hi;
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) {
@@ -147,60 +211,145 @@ void k_band(BandArgs a)
         u0 = o0 < u0 ? o0 : u0;
         u1 = o1 > u1 ? o1 : u1;
     }
+    if (lane == 0) {
+        wspan[0][wv] = u0;
+        wspan[1][wv] = u1;
+    }
+    __syncthreads();
+    uint64_t U0 = ~0ull, U1 = 0;
+#pragma unroll
+    for (int i = 0; i < kMW; i++) {
+        U0 = wspan[0][i] < U0 ? wspan[0][i] : U0;
+        U1 = wspan[1][i] > U1 ? wspan[1][i] : U1;
+    }
 
     uint64_t L[KR];
 #pragma unroll
     for (int i = 0; i < KR; i++) L[i] = kNone;
+
+    // Tiles are taken from the middle of the union outwards: the entries
+    // nearest the queries' places come first and fill the lists with close
+    // candidates early, so that fewer later sums pass the list bound.
+    const uint32_t T = U0 < U1 ? (uint32_t)((U1 - U0 + kMRows - 1) / kMRows) : 0u;
+    const uint32_t jm = T ? (uint32_t)(((U1 - U0) / 2) / kMRows) : 0u;
+    const uint32_t nleft = jm, nright = T ? T - 1 - jm : 0u;
+    const uint32_t nboth = nleft < nright ? nleft : nright;
+    auto tile_start = [&](uint32_t i) -> uint64_t {
+        uint32_t j;
+        if (i <= 2 * nboth) j = (i & 1) ? jm + (i + 1) / 2 : jm - i / 2;
+        else j = nright > nleft ? jm + (i - nboth) : jm - (i - nboth);
+        return U0 + (uint64_t)j * kMRows;
+    };
+
+    // loader: thread t fills 32 bytes (parts 2f, 2f + 1) of tile row t / 4;
+    // the ids run two tiles ahead of the rows, the rows one tile ahead of the
+    // matrix work
     const uint32_t *ids = a.v.ids[c];
-    const int part = lane & 7, rsub = lane >> 3;
-    for (uint64_t t0 = u0; t0 < u1; t0 += kBandRows) {
-        const uint32_t rows = (uint32_t)std::min<uint64_t>(kBandRows, u1 - t0);
-        // load: lane l takes the id of entry t0 + l; in step s, lanes 8r..8r+7
-        // read the 16-byte parts of row 8s + r
-        const uint32_t myid = (uint32_t)lane < rows ? ids[t0 + lane] : 0u;
-        __syncthreads();
-        if ((uint32_t)lane < rows) tile_id[lane] = myid;
+    const uint32_t lr = (uint32_t)tid >> 2, lf = (uint32_t)tid & 3;
+    auto load_id = [&](uint32_t i) -> uint32_t {
+        const uint64_t e = tile_start(i) + lr;
+        return e < U1 ? ids[e] : kEmpty;
+    };
+    // rows past the union (the last tile's tail) read row 0: they lie outside
+    // every window and are never offered
+    uint4 x0 = make_uint4(0, 0, 0, 0), x1 = x0;
+    auto load_row = [&](uint32_t id) {
+        const uint64_t r = id != kEmpty ? id : 0u;
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.v.db + r * kDim) + 2 * lf;
+        x0 = src[0];
+        x1 = src[1];
+    };
+    uint32_t xid = T > 0 ? load_id(0) : kEmpty;
+    uint32_t id_next = T > 1 ? load_id(1) : kEmpty;
+    if (T > 0) load_row(xid);
+
+    for (uint32_t i = 0; i < T; i++) {
+        const uint64_t t0 = tile_start(i);
+        {   // publish the fetched rows
+            uint32_t xx = 0, sx = 0;
+            const uint32_t parts[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
 #pragma unroll
-        for (int s = 0; s < 8; s++) {
-            const uint32_t r = 8 * s + rsub;
-            const uint32_t rid = __shfl(myid, r, 64);
-            uint4 x = make_uint4(0, 0, 0, 0);
-            if (r < rows) x = *reinterpret_cast<const uint4 *>(a.v.db + (uint64_t)rid * kDim +
-                                                               16 * part);
-            tile[r * 8 + part] = x;
-            uint32_t xx = __builtin_amdgcn_udot4(x.x, x.x, 0u, false);
-            xx = __builtin_amdgcn_udot4(x.y, x.y, xx, false);
-            xx = __builtin_amdgcn_udot4(x.z, x.z, xx, false);
-            xx = __builtin_amdgcn_udot4(x.w, x.w, xx, false);
-            xx += __shfl_xor(xx, 1, 64);
-            xx += __shfl_xor(xx, 2, 64);
-            xx += __shfl_xor(xx, 4, 64);
-            if (part == 0) tile_xx[r] = xx;
-        }
-        __syncthreads();
-        for (uint32_t r = 0; r < rows; r++) {
-            const uint64_t e = t0 + r;
-            uint32_t qx = 0;
-#pragma unroll
-            for (int i = 0; i < 8; i++) {
-                const uint4 x = tile[r * 8 + i];
-                qx = __builtin_amdgcn_udot4(qv[i].x, x.x, qx, false);
-                qx = __builtin_amdgcn_udot4(qv[i].y, x.y, qx, false);
-                qx = __builtin_amdgcn_udot4(qv[i].z, x.z, qx, false);
-                qx = __builtin_amdgcn_udot4(qv[i].w, x.w, qx, false);
+            for (int m = 0; m < 8; m++) {
+                xx = __builtin_amdgcn_udot4(parts[m], parts[m], xx, false);
+                sx = __builtin_amdgcn_udot4(parts[m], 0x01010101u, sx, false);
             }
-            const uint32_t d = qq + tile_xx[r] - 2u * qx;
-            const uint64_t key = (e >= lo && e < hi) ? (((uint64_t)d << 32) | tile_id[r]) : kNone;
-            // ids are distinct within one list: a plain sorted insert
-            if (key < L[KR - 1]) {
+            xx += __shfl_xor(xx, 1, 64);
+            sx += __shfl_xor(sx, 1, 64);
+            xx += __shfl_xor(xx, 2, 64);
+            sx += __shfl_xor(sx, 2, 64);
+            __syncthreads();
+            tile[mslot(lr, 2 * lf)] = xor4(x0, 0x7F7F7F7Fu);
+            tile[mslot(lr, 2 * lf + 1)] = xor4(x1, 0x7F7F7F7Fu);
+            if (lf == 0) {
+                tile_c[lr] = (int)(xx - 256u * sx);
+                tile_id[lr] = xid;
+            }
+            __syncthreads();
+        }
+        if (i + 1 < T) {
+            xid = id_next;
+            load_row(xid);
+        }
+        if (i + 2 < T) id_next = load_id(i + 2);
+        if (!(t0 < u1 && t0 + kMRows > u0)) continue;       // wavefront-uniform
+
+        const int own = list_bound(L, cq);
+        int th = own;
+        {
+            const int other = __shfl_xor(own, 32, 64);
+            th = other < th ? other : th;
+        }
+        if (!live || !(t0 < hi && t0 + kMRows > lo)) th = INT32_MIN;
+#pragma unroll 1
+        for (uint32_t rb = 0; rb < kMRows / 32; rb++) {
+            v16i acc = {};
+            const uint32_t ar = rb * 32 + qn;
 #pragma unroll
-                for (int i = KR - 1; i > 0; i--)
-                    L[i] = key < L[i - 1] ? L[i - 1] : (key < L[i] ? key : L[i]);
-                L[0] = key < L[0] ? key : L[0];
+            for (int s = 0; s < 4; s++) {
+                const uint4 av = tile[mslot(ar, 2 * s + h)];
+                acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                    v4i{(int)av.x, (int)av.y, (int)av.z, (int)av.w}, bq[s], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int g = 0; g < 4; g++) {
+                const uint32_t r0 = rb * 32 + 8 * g + 4 * h;
+                const int4 cr = *reinterpret_cast<const int4 *>(&tile_c[r0]);
+                const int crv[4] = {cr.x, cr.y, cr.z, cr.w};
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const int t = (acc[4 * g + j] << 1) + crv[j];
+                    if (t <= th) {
+                        const uint64_t e = t0 + r0 + j;
+                        if (e >= lo && e < hi) {
+                            const uint64_t key =
+                                ((uint64_t)(uint32_t)(t + cq) << 32) | tile_id[r0 + j];
+                            if (key < L[KR - 1]) {
+#pragma unroll
+                                for (int i = KR - 1; i > 0; i--)
+                                    L[i] = key < L[i - 1] ? L[i - 1] : (key < L[i] ? key : L[i]);
+                                L[0] = key < L[0] ? key : L[0];
+                                const int b = list_bound(L, cq);
+                                th = b < th ? b : th;
+                            }
+                        }
+                    }
+                }
             }
         }
     }
-    if (live) {
+
+    // lane qn takes the other half's list (rows of one list: ids distinct)
+#pragma unroll
+    for (int i = 0; i < KR; i++) {
+        const uint64_t o = shfl_xor_u64(L[i], 32);
+        if (h == 0 && o < L[KR - 1]) {
+#pragma unroll
+            for (int j = KR - 1; j > 0; j--)
+                L[j] = o < L[j - 1] ? L[j - 1] : (o < L[j] ? o : L[j]);
+            L[0] = o < L[0] ? o : L[0];
+        }
+    }
+    if (live && h == 0) {
         uint64_t *out = a.partial + ((uint64_t)q * C + c) * a.k;
 #pragma unroll
         for (int i = 0; i < KR; i++)
@@ -267,11 +416,12 @@ hc_status band_search(const IndexView &v, const uint8_t *d_queries, uint32_t nq,
     hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(kScanThreads), 0, st, a.counts, nc);
     const uint64_t nt = (uint64_t)nq * v.curves;
     hipLaunchKernelGGL(k_band_scatter, dim3((uint32_t)((nt + 255) / 256)), dim3(256), 0, st, a);
-    const dim3 grid((nq + 63) / 64, v.curves);
-    if (k == 1) hipLaunchKernelGGL(k_band<1>, grid, dim3(64), 0, st, a);
-    else if (k <= 4) hipLaunchKernelGGL(k_band<4>, grid, dim3(64), 0, st, a);
-    else if (k <= 10) hipLaunchKernelGGL(k_band<10>, grid, dim3(64), 0, st, a);
-    else hipLaunchKernelGGL(k_band<kBandK>, grid, dim3(64), 0, st, a);
+    const uint32_t blocks = (uint32_t)(((uint64_t)nq + kMBlockQ - 1) / kMBlockQ) * v.curves;
+    const dim3 grid(blocks), block(kMThreads);
+    if (k == 1) hipLaunchKernelGGL(k_band<1>, grid, block, 0, st, a);
+    else if (k <= 4) hipLaunchKernelGGL(k_band<4>, grid, block, 0, st, a);
+    else if (k <= 10) hipLaunchKernelGGL(k_band<10>, grid, block, 0, st, a);
+    else hipLaunchKernelGGL(k_band<kBandK>, grid, block, 0, st, a);
     hipLaunchKernelGGL(k_band_merge, dim3(nq), dim3(64), 0, st, a);
     return last_hip();
 }
