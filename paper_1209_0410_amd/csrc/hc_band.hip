@@ -41,11 +41,12 @@ struct BandArgs {
     uint32_t nbuckets;
     uint32_t *order;      // [curves][nq]
     uint64_t *partial;    // [q][curves][k]
+    uint32_t *bound;      // [q]: least k-th distance of the curves done so far
     uint32_t *out_ids, *out_dists;
 };
 
 struct BandLayout {
-    size_t qkeys, pos, counts, order, partial, total;
+    size_t qkeys, pos, counts, order, partial, bound, total;
     uint32_t nbuckets;
 };
 
@@ -64,15 +65,17 @@ inline BandLayout band_layout(uint32_t curves, uint64_t n, uint32_t nq)
     off = align256(off + sizeof(uint32_t) * (size_t)curves * nq);
     L.partial = off;
     off = align256(off + sizeof(uint64_t) * (size_t)nq * curves * kBandK);
+    L.bound = off;
+    off = align256(off + sizeof(uint32_t) * (size_t)nq);
     L.total = off;
     return L;
 }
 
-__global__ __launch_bounds__(256) void k_band_zero(uint32_t *p, uint64_t n)
+__global__ __launch_bounds__(256) void k_band_fill(uint32_t *p, uint64_t n, uint32_t value)
 {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
-        p[i] = 0;
+        p[i] = value;
 }
 
 // One wavefront per query: its place in every curve, counted into buckets.
@@ -150,9 +153,12 @@ __device__ inline int list_bound(const uint64_t (&L)[KR], int cq)
     return L[KR - 1] == kNone ? INT32_MAX : (int)(uint32_t)(L[KR - 1] >> 32) - cq;
 }
 
-// 1-D grid of groups * curves blocks.  Consecutive blocks go to different
-// XCDs; the mapping gives each XCD a run of neighbouring groups of one curve,
-// whose windows overlap, so that their rows meet in that XCD's L2.
+// 1-D grid of groups * curves blocks, curve-major: the curves are worked
+// through one after another, so that most blocks start with a bound on the
+// k-th distance of their queries from the curves already done.  Any such
+// bound is safe: a curve's list holds k distinct candidates of the union, so
+// the final k-th distance is at most its k-th distance, and a sum above the
+// bound cannot reach the result.  The results do not depend on the timing.
 template <int KR>
 __global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(KR > 10 ? 3 : 4)))
 void k_band(BandArgs a)
@@ -167,10 +173,7 @@ void k_band(BandArgs a)
     const uint32_t C = a.v.curves;
     const uint64_t n = a.v.n;
     const uint32_t groups = (a.nq + kMBlockQ - 1) / kMBlockQ;
-    const uint32_t nb = groups * C;
-    const uint32_t per = nb / 8, rem = nb % 8, xcd = blockIdx.x % 8, idx = blockIdx.x / 8;
-    const uint32_t bb = xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
-    const uint32_t grp = bb % groups, c = bb / groups;
+    const uint32_t grp = blockIdx.x % groups, c = blockIdx.x / groups;
 
     // this lane's query: B operand (16-byte parts 2s + h), cq, window
     const uint64_t slot = (uint64_t)grp * kMBlockQ + (uint64_t)wv * kMQ + qn;
@@ -226,6 +229,19 @@ void k_band(BandArgs a)
     uint64_t L[KR];
 #pragma unroll
     for (int i = 0; i < KR; i++) L[i] = kNone;
+    // bound from the other curves, in the sum's terms (sum = distance - cq)
+    int ext = INT32_MAX;
+    auto read_bound = [&]() {
+        if (live) {
+            const uint32_t b = __hip_atomic_load(a.bound + q, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            if (b != kEmpty) {
+                const int e = (int)b - cq;
+                ext = e < ext ? e : ext;
+            }
+        }
+    };
+    read_bound();
 
     // Tiles are taken from the middle of the union outwards: the entries
     // nearest the queries' places come first and fill the lists with close
@@ -291,15 +307,21 @@ void k_band(BandArgs a)
             load_row(xid);
         }
         if (i + 2 < T) id_next = load_id(i + 2);
+        if ((i & 7) == 7) read_bound();
         if (!(t0 < u1 && t0 + kMRows > u0)) continue;       // wavefront-uniform
 
+        // this lane's bound: its list, the other half's list, the other curves
         const int own = list_bound(L, cq);
         int th = own;
         {
             const int other = __shfl_xor(own, 32, 64);
             th = other < th ? other : th;
+            th = ext < th ? ext : th;
         }
-        if (!live || !(t0 < hi && t0 + kMRows > lo)) th = INT32_MIN;
+        // the window as tile rows [rlo, rhi)
+        const uint32_t rlo = lo > t0 ? (uint32_t)std::min<uint64_t>(lo - t0, kMRows) : 0u;
+        const uint32_t rhi = hi > t0 ? (uint32_t)std::min<uint64_t>(hi - t0, kMRows) : 0u;
+        if (!live || rlo >= rhi) th = INT32_MIN;
 #pragma unroll 1
         for (uint32_t rb = 0; rb < kMRows / 32; rb++) {
             v16i acc = {};
@@ -314,19 +336,19 @@ void k_band(BandArgs a)
             for (int g = 0; g < 4; g++) {
                 const uint32_t r0 = rb * 32 + 8 * g + 4 * h;
                 const int4 cr = *reinterpret_cast<const int4 *>(&tile_c[r0]);
-                const int crv[4] = {cr.x, cr.y, cr.z, cr.w};
+                const int t[4] = {(acc[4 * g] << 1) + cr.x, (acc[4 * g + 1] << 1) + cr.y,
+                                  (acc[4 * g + 2] << 1) + cr.z, (acc[4 * g + 3] << 1) + cr.w};
+                const int tmin = std::min(std::min(t[0], t[1]), std::min(t[2], t[3]));
+                if (tmin <= th) {       // rare once the lists are full
 #pragma unroll
-                for (int j = 0; j < 4; j++) {
-                    const int t = (acc[4 * g + j] << 1) + crv[j];
-                    if (t <= th) {
-                        const uint64_t e = t0 + r0 + j;
-                        if (e >= lo && e < hi) {
+                    for (int j = 0; j < 4; j++) {
+                        if (t[j] <= th && r0 + j - rlo < rhi - rlo) {
                             const uint64_t key =
-                                ((uint64_t)(uint32_t)(t + cq) << 32) | tile_id[r0 + j];
+                                ((uint64_t)(uint32_t)(t[j] + cq) << 32) | tile_id[r0 + j];
                             if (key < L[KR - 1]) {
 #pragma unroll
-                                for (int i = KR - 1; i > 0; i--)
-                                    L[i] = key < L[i - 1] ? L[i - 1] : (key < L[i] ? key : L[i]);
+                                for (int m = KR - 1; m > 0; m--)
+                                    L[m] = key < L[m - 1] ? L[m - 1] : (key < L[m] ? key : L[m]);
                                 L[0] = key < L[0] ? key : L[0];
                                 const int b = list_bound(L, cq);
                                 th = b < th ? b : th;
@@ -351,9 +373,13 @@ void k_band(BandArgs a)
     }
     if (live && h == 0) {
         uint64_t *out = a.partial + ((uint64_t)q * C + c) * a.k;
+        uint64_t kth = kNone;
 #pragma unroll
-        for (int i = 0; i < KR; i++)
+        for (int i = 0; i < KR; i++) {
             if ((uint32_t)i < a.k) out[i] = L[i];
+            if ((uint32_t)i == a.k - 1) kth = L[i];
+        }
+        if (kth != kNone) atomicMin(a.bound + q, (uint32_t)(kth >> 32));
     }
 }
 
@@ -407,11 +433,14 @@ hc_status band_search(const IndexView &v, const uint8_t *d_queries, uint32_t nq,
     a.nbuckets = L.nbuckets;
     a.order = (uint32_t *)(s + L.order);
     a.partial = (uint64_t *)(s + L.partial);
+    a.bound = (uint32_t *)(s + L.bound);
     a.out_ids = d_out_ids;
     a.out_dists = d_out_dists;
     const uint64_t nc = (uint64_t)v.curves * L.nbuckets;
-    hipLaunchKernelGGL(k_band_zero, dim3((uint32_t)std::min<uint64_t>(4096, (nc + 255) / 256)),
-                       dim3(256), 0, st, a.counts, nc);
+    hipLaunchKernelGGL(k_band_fill, dim3((uint32_t)std::min<uint64_t>(4096, (nc + 255) / 256)),
+                       dim3(256), 0, st, a.counts, nc, 0u);
+    hipLaunchKernelGGL(k_band_fill, dim3((uint32_t)std::min<uint64_t>(4096, (nq + 255) / 256)),
+                       dim3(256), 0, st, a.bound, (uint64_t)nq, kEmpty);
     hipLaunchKernelGGL(k_band_place, dim3(nq), dim3(64), 0, st, a);
     hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(kScanThreads), 0, st, a.counts, nc);
     const uint64_t nt = (uint64_t)nq * v.curves;
