@@ -30,9 +30,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# dot4 peak of the vector ALUs: 256 CUs x 64 lanes x 4 int8 MACs per lane per
-# cycle x 2 ops per MAC x 2.4 GHz
-ALU_PEAK_TOPS = 256 * 64 * 4 * 2 * 2.4e9 / 1e12
+# MI355X dense int8 matrix-core peak (the banded path's distances are int8
+# MFMA products)
+MFMA_I8_PEAK_TOPS = 5000.0
 TARGET = 0.90
 CALIB_TARGET = 0.905    # margin for the sampling error of the evaluation recall
 
@@ -257,8 +257,8 @@ def main():
         "uneven": uneven,
         "roofline": roofline(head),
     }
-    if head is fixed and head["path"] == "gather":
-        tb, tsrc = counted_traffic(a.n, a.nq, k, w_fix)
+    if head is fixed:
+        tb, tsrc = counted_traffic(a.n, a.nq, k, w_fix, head["path"])
         if tb is not None:
             result["roofline"]["traffic"] = tb
             result["roofline"]["traffic_source"] = tsrc
@@ -330,32 +330,44 @@ def path_name(p):
 
 
 def roofline(head):
-    """Roofline of the search call (hc_search_encoded): HBM-bound on the gather
-    path (window ids + distinct rows + results per launch), ALU-bound on the
-    banded path (2 x 128 int8 MAC-ops per distinct candidate per launch)."""
+    """Roofline of the search call (hc_search_encoded, timed with HIP events on
+    its stream): HBM-bound on the gather path (window ids + distinct rows +
+    results per call); on the banded path the distances are int8 matrix-core
+    products, 2 x 128 ops per distinct candidate per call, against the dense
+    int8 MFMA peak."""
     if head["path"] == "gather":
         return {"bound": "hbm", "achieved": head["alg_GBs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": head["alg_GBs"] / HBM_PEAK_GBS, "traffic": None,
                 "kernel": "k_stream (hc_search_encoded, gather path)",
                 "kernel_ms": head["kernel_ms"], "alg_bytes_per_launch": head["alg_bytes"]}
-    return {"bound": "alu", "achieved": head["alg_TOPs"], "peak": ALU_PEAK_TOPS,
-            "unit": "TOP/s", "frac": head["alg_TOPs"] / ALU_PEAK_TOPS, "traffic": None,
-            "kernel": "k_band + place/sort/merge (hc_search_encoded, banded path)",
+    return {"bound": "mfma", "achieved": head["alg_TOPs"], "peak": MFMA_I8_PEAK_TOPS,
+            "unit": "TOP/s", "frac": head["alg_TOPs"] / MFMA_I8_PEAK_TOPS, "traffic": None,
+            "kernel": "k_band with k_band_place/k_scan_excl/k_band_scatter/k_band_merge "
+                      "(hc_search_encoded, banded path)",
             "kernel_ms": head["kernel_ms"],
-            "alg_ops_per_launch": head["alg_TOPs"] * 1e12 * head["kernel_ms"] * 1e-3,
-            "hbm_alg_GBs": head["alg_GBs"]}
+            "alg_ops_per_launch": head["alg_TOPs"] * 1e12 * head["kernel_ms"] * 1e-3}
 
 
-def counted_traffic(n, nq, k, w):
-    """HBM bytes per search launch from the committed rocprofv3 counter summary of
-    this workload, if its kernel sources are the ones built here; else None."""
-    import glob
+KERNEL_SOURCES = {"gather": ("k_stream", ("hc_search.hip", "hc_device.h")),
+                  "band": ("k_band", ("hc_band.hip", "hc_search.hip", "hc_device.h",
+                                      "hc_scan.h"))}
+
+
+def sources_md5(path):
     import hashlib
     src = os.path.join(ROOT, "paper_1209_0410_amd", "csrc")
-    md5 = hashlib.md5(b"".join(open(os.path.join(src, f), "rb").read()
-                                for f in ("hc_search.hip", "hc_device.h"))).hexdigest()
+    return hashlib.md5(b"".join(open(os.path.join(src, f), "rb").read()
+                                for f in KERNEL_SOURCES[path][1])).hexdigest()
+
+
+def counted_traffic(n, nq, k, w, path):
+    """HBM bytes per search call from the committed rocprofv3 counter summary of
+    this workload, if its kernel sources are the ones built here; else None."""
+    import glob
+    md5 = sources_md5(path)
     want = f"workload: n={n} nq={nq} k={k} w={w}"
-    for path in glob.glob(os.path.join(ROOT, "profiles", "k_stream_*_counters.md")):
+    kern = KERNEL_SOURCES[path][0]
+    for path in glob.glob(os.path.join(ROOT, "profiles", f"{kern}_*_counters.md")):
         text = open(path).read()
         if want not in text or f"kernel_sources_md5: {md5}" not in text:
             continue

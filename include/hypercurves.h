@@ -166,7 +166,7 @@ hc_status hc_search_encoded(const hc_index *idx, const uint8_t *d_queries, uint3
  *                  query keeps the entries inside its own window (for large
  *                  batches with large windows, where one list entry lies in
  *                  many windows).  k <= 16.
- *  HC_PATH_AUTO:   banded when 2 w nq >= 10 n (w = w_fixed or the hint), k <= 16
+ *  HC_PATH_AUTO:   banded when 2 w nq >= 6 n (w = w_fixed or the hint), k <= 16
  *                  and the scratch holds hc_search_scratch_bytes; else gather.
  * hc_search_encoded is hc_search_encoded_ex with HC_PATH_AUTO. */
 #define HC_PATH_AUTO 0u

@@ -134,6 +134,7 @@ constexpr int kMQ = 32;             // queries per wavefront
 constexpr int kMRows = 128;         // list entries per LDS tile
 constexpr int kMThreads = 64 * kMW;
 constexpr int kMBlockQ = kMW * kMQ;
+constexpr uint32_t kNoRow = 0xFFFFFFFFu;
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
@@ -166,7 +167,7 @@ void k_band(BandArgs a)
     __shared__ uint4 tile[kMRows * 8];
     __shared__ __align__(16) int tile_c[kMRows];
     __shared__ uint32_t tile_id[kMRows];
-    __shared__ uint64_t wspan[2][kMW];
+    __shared__ uint32_t wspan[2][kMW];
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int h = lane >> 5, qn = lane & 31;
@@ -201,16 +202,20 @@ void k_band(BandArgs a)
     qq += __shfl_xor(qq, 32, 64);
     sq += __shfl_xor(sq, 32, 64);
     const int cq = (int)(qq - 254u * sq + 4161536u);
-    const uint64_t w = live ? (a.d_w ? a.d_w[q] : a.w_fixed) : 0;
-    const uint64_t p = live ? a.pos[(uint64_t)q * C + c] : 0;
-    const uint64_t lo = live ? (p > w ? p - w : 0) : ~0ull;
-    const uint64_t hi = live ? (p + w < n ? p + w : n) : 0;
+    // list places fit 32 bits (n < 2^32 - 1)
+    uint32_t lo, hi;
+    {
+        const uint64_t w = live ? (a.d_w ? a.d_w[q] : a.w_fixed) : 0;
+        const uint64_t p = live ? a.pos[(uint64_t)q * C + c] : 0;
+        lo = live ? (uint32_t)(p > w ? p - w : 0) : 0xFFFFFFFFu;
+        hi = live ? (uint32_t)(p + w < n ? p + w : n) : 0u;
+    }
 
     // unions of the wavefront's and of the block's windows
-    uint64_t u0 = lo, u1 = hi;
+    uint32_t u0 = lo, u1 = hi;
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) {
-        const uint64_t o0 = shfl_xor_u64(u0, m), o1 = shfl_xor_u64(u1, m);
+        const uint32_t o0 = __shfl_xor(u0, m, 64), o1 = __shfl_xor(u1, m, 64);
         u0 = o0 < u0 ? o0 : u0;
         u1 = o1 > u1 ? o1 : u1;
     }
@@ -219,7 +224,7 @@ void k_band(BandArgs a)
         wspan[1][wv] = u1;
     }
     __syncthreads();
-    uint64_t U0 = ~0ull, U1 = 0;
+    uint32_t U0 = 0xFFFFFFFFu, U1 = 0;
 #pragma unroll
     for (int i = 0; i < kMW; i++) {
         U0 = wspan[0][i] < U0 ? wspan[0][i] : U0;
@@ -246,15 +251,15 @@ void k_band(BandArgs a)
     // Tiles are taken from the middle of the union outwards: the entries
     // nearest the queries' places come first and fill the lists with close
     // candidates early, so that fewer later sums pass the list bound.
-    const uint32_t T = U0 < U1 ? (uint32_t)((U1 - U0 + kMRows - 1) / kMRows) : 0u;
+    const uint32_t T = U0 < U1 ? (uint32_t)(((uint64_t)U1 - U0 + kMRows - 1) / kMRows) : 0u;
     const uint32_t jm = T ? (uint32_t)(((U1 - U0) / 2) / kMRows) : 0u;
     const uint32_t nleft = jm, nright = T ? T - 1 - jm : 0u;
     const uint32_t nboth = nleft < nright ? nleft : nright;
-    auto tile_start = [&](uint32_t i) -> uint64_t {
+    auto tile_start = [&](uint32_t i) -> uint32_t {
         uint32_t j;
         if (i <= 2 * nboth) j = (i & 1) ? jm + (i + 1) / 2 : jm - i / 2;
         else j = nright > nleft ? jm + (i - nboth) : jm - (i - nboth);
-        return U0 + (uint64_t)j * kMRows;
+        return U0 + j * kMRows;
     };
 
     // loader: thread t fills 32 bytes (parts 2f, 2f + 1) of tile row t / 4;
@@ -263,7 +268,7 @@ void k_band(BandArgs a)
     const uint32_t *ids = a.v.ids[c];
     const uint32_t lr = (uint32_t)tid >> 2, lf = (uint32_t)tid & 3;
     auto load_id = [&](uint32_t i) -> uint32_t {
-        const uint64_t e = tile_start(i) + lr;
+        const uint64_t e = (uint64_t)tile_start(i) + lr;
         return e < U1 ? ids[e] : kEmpty;
     };
     // rows past the union (the last tile's tail) read row 0: they lie outside
@@ -280,7 +285,7 @@ void k_band(BandArgs a)
     if (T > 0) load_row(xid);
 
     for (uint32_t i = 0; i < T; i++) {
-        const uint64_t t0 = tile_start(i);
+        const uint32_t t0 = tile_start(i);
         {   // publish the fetched rows
             uint32_t xx = 0, sx = 0;
             const uint32_t parts[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
@@ -308,7 +313,7 @@ void k_band(BandArgs a)
         }
         if (i + 2 < T) id_next = load_id(i + 2);
         if ((i & 7) == 7) read_bound();
-        if (!(t0 < u1 && t0 + kMRows > u0)) continue;       // wavefront-uniform
+        if (!(t0 < u1 && (uint64_t)t0 + kMRows > u0)) continue;       // wavefront-uniform
 
         // this lane's bound: its list, the other half's list, the other curves
         const int own = list_bound(L, cq);
@@ -319,9 +324,26 @@ void k_band(BandArgs a)
             th = ext < th ? ext : th;
         }
         // the window as tile rows [rlo, rhi)
-        const uint32_t rlo = lo > t0 ? (uint32_t)std::min<uint64_t>(lo - t0, kMRows) : 0u;
-        const uint32_t rhi = hi > t0 ? (uint32_t)std::min<uint64_t>(hi - t0, kMRows) : 0u;
+        const uint32_t rlo = lo > t0 ? std::min<uint32_t>(lo - t0, kMRows) : 0u;
+        const uint32_t rhi = hi > t0 ? std::min<uint32_t>(hi - t0, kMRows) : 0u;
         if (!live || rlo >= rhi) th = INT32_MIN;
+        // A passing sum waits in a pending slot (its sum and tile row) and
+        // is inserted at the end of the tile, when the whole wavefront inserts
+        // at once; a lane inserts early only when a second sum passes.
+        int pend_t = 0;
+        uint32_t pend_r = kNoRow;
+        auto insert_pending = [&]() {
+            const uint64_t key = ((uint64_t)(uint32_t)(pend_t + cq) << 32) | tile_id[pend_r];
+            if (key < L[KR - 1]) {
+#pragma unroll
+                for (int m = KR - 1; m > 0; m--)
+                    L[m] = key < L[m - 1] ? L[m - 1] : (key < L[m] ? key : L[m]);
+                L[0] = key < L[0] ? key : L[0];
+                const int b = list_bound(L, cq);
+                th = b < th ? b : th;
+            }
+            pend_r = kNoRow;
+        };
 #pragma unroll 1
         for (uint32_t rb = 0; rb < kMRows / 32; rb++) {
             v16i acc = {};
@@ -343,21 +365,15 @@ void k_band(BandArgs a)
 #pragma unroll
                     for (int j = 0; j < 4; j++) {
                         if (t[j] <= th && r0 + j - rlo < rhi - rlo) {
-                            const uint64_t key =
-                                ((uint64_t)(uint32_t)(t[j] + cq) << 32) | tile_id[r0 + j];
-                            if (key < L[KR - 1]) {
-#pragma unroll
-                                for (int m = KR - 1; m > 0; m--)
-                                    L[m] = key < L[m - 1] ? L[m - 1] : (key < L[m] ? key : L[m]);
-                                L[0] = key < L[0] ? key : L[0];
-                                const int b = list_bound(L, cq);
-                                th = b < th ? b : th;
-                            }
+                            if (pend_r != kNoRow) insert_pending();
+                            pend_t = t[j];
+                            pend_r = r0 + j;
                         }
                     }
                 }
             }
         }
+        if (pend_r != kNoRow) insert_pending();
     }
 
     // lane qn takes the other half's list (rows of one list: ids distinct)
