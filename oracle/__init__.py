@@ -30,18 +30,20 @@ _dbl = ct.c_double
 _SIGS = {
     "hco_hilbert_encode": [_u32p, _i64, _int, _int, _u64p, _u64p],
     "hco_hilbert_decode": [_u64p, _u64p, _i64, _int, _int, _u32p],
-    "hco_keys": [_u8p, _i64, _int, _u16p, _int, _int, _int, _u64p, _u64p],
-    "hco_build": [_u8p, _i64, _int, _u16p, _int, _int, _int, _u64p, _u64p, _u32p],
-    "hco_positions": [_u64p, _u64p, _i64, _int, _u16p, _int, _int, _int, _u8p, _i64,
+    "hco_zorder_encode": [_u32p, _i64, _int, _int, _u64p, _u64p],
+    "hco_zorder_decode": [_u64p, _u64p, _i64, _int, _int, _u32p],
+    "hco_keys_ex": [_u8p, _i64, _int, _u16p, _int, _int, _int, _int, _u64p, _u64p],
+    "hco_build_ex": [_u8p, _i64, _int, _u16p, _int, _int, _int, _int, _u64p, _u64p, _u32p],
+    "hco_positions": [_u64p, _u64p, _i64, _int, _u16p, _int, _int, _int, _int, _u8p, _i64,
                       _i64p],
-    "hco_candidates": [_u64p, _u64p, _u32p, _i64, _int, _u16p, _int, _int, _int, _u8p,
-                       _i64, _u32p, _u32p, _u32p, _i64],
-    "hco_search": [_u64p, _u64p, _u32p, _u8p, _i64, _int, _u16p, _int, _int, _int, _u8p,
-                   _i64, _int, _u32p, _u32p, _u32p],
+    "hco_candidates": [_u64p, _u64p, _u32p, _i64, _int, _u16p, _int, _int, _int, _int,
+                       _u8p, _i64, _u32p, _u32p, _u32p, _i64],
+    "hco_search": [_u64p, _u64p, _u32p, _u8p, _i64, _int, _u16p, _int, _int, _int, _int,
+                   _u8p, _i64, _int, _u32p, _u32p, _u32p],
     "hco_brute_force": [_u8p, _i64, _int, _u8p, _i64, _int, _u32p, _u32p],
-    "hco_labels": [_u64p, _u64p, _u32p, _i64, _int, _u16p, _int, _int, _int, _u8p, _i64,
-                   _int, _u32p, _u32p],
-    "hco_features": [_u64p, _u64p, _u32p, _u8p, _i64, _int, _u16p, _int, _int, _int,
+    "hco_labels": [_u64p, _u64p, _u32p, _i64, _int, _u16p, _int, _int, _int, _int, _u8p,
+                   _i64, _int, _u32p, _u32p],
+    "hco_features": [_u64p, _u64p, _u32p, _u8p, _i64, _int, _u16p, _int, _int, _int, _int,
                      _u8p, _i64, _u32p, _f64p],
     "hco_mlp_forward": [_f64p, _f64p, _i64, _int, _int, _int, _f64p],
     "hco_mlp_loss_grad": [_f64p, _f64p, _f64p, _i64, _int, _int, _int, _f64p,
@@ -100,6 +102,24 @@ def hilbert_decode(hi, lo, n, bits):
     return out
 
 
+def zorder_encode(coords, bits):
+    """coords: (P, n) uint -> (hi, lo) uint64 arrays of the Z-order key."""
+    c = _c(coords, np.uint32)
+    P, n = c.shape
+    hi = np.zeros(P, np.uint64)
+    lo = np.zeros(P, np.uint64)
+    _check(lib().hco_zorder_encode(c, P, n, bits, hi, lo), "zorder_encode")
+    return hi, lo
+
+
+def zorder_decode(hi, lo, n, bits):
+    hi = _c(hi, np.uint64)
+    lo = _c(lo, np.uint64)
+    out = np.zeros((hi.shape[0], n), np.uint32)
+    _check(lib().hco_zorder_decode(hi, lo, hi.shape[0], n, bits, out), "zorder_decode")
+    return out
+
+
 def key_int(hi, lo):
     """Python int of a (hi, lo) pair."""
     return (int(hi) << 64) | int(lo)
@@ -109,14 +129,19 @@ def key_int(hi, lo):
 # Index
 # ---------------------------------------------------------------------------
 
-class Params:
-    """Curves, dims per curve and the dimension assignment of Alg. 1."""
+CURVES = {"hilbert": 0, "zorder": 1}
 
-    def __init__(self, dim=128, curves=8, dpc=16, perm=None):
+
+class Params:
+    """Curves, dims per curve, the dimension assignment of Alg. 1 and the kind
+    of space-filling curve ("hilbert", the paper's, or "zorder")."""
+
+    def __init__(self, dim=128, curves=8, dpc=16, perm=None, curve="hilbert"):
         self.dim, self.curves, self.dpc, self.bits = dim, curves, dpc, 8
         if perm is None:
             perm = np.arange(curves * dpc)
         self.perm = _c(perm, np.uint16)
+        self.curve = CURVES[curve]
 
 
 def keys(rows, p: Params):
@@ -125,7 +150,8 @@ def keys(rows, p: Params):
     R = r.shape[0]
     hi = np.zeros((R, p.curves), np.uint64)
     lo = np.zeros((R, p.curves), np.uint64)
-    _check(lib().hco_keys(r, R, p.dim, p.perm, p.curves, p.dpc, p.bits, hi, lo), "keys")
+    _check(lib().hco_keys_ex(r, R, p.dim, p.perm, p.curves, p.dpc, p.bits, p.curve, hi, lo),
+           "keys")
     return hi, lo
 
 
@@ -140,8 +166,9 @@ class Index:
         self.hi = np.zeros((C, self.n), np.uint64)
         self.lo = np.zeros((C, self.n), np.uint64)
         self.ids = np.zeros((C, self.n), np.uint32)
-        _check(lib().hco_build(self.db, self.n, self.p.dim, self.p.perm, C, self.p.dpc,
-                               self.p.bits, self.hi, self.lo, self.ids), "build")
+        _check(lib().hco_build_ex(self.db, self.n, self.p.dim, self.p.perm, C, self.p.dpc,
+                                  self.p.bits, self.p.curve, self.hi, self.lo, self.ids),
+               "build")
 
     def _args(self):
         p = self.p
@@ -155,7 +182,7 @@ class Index:
         p = self.p
         out = np.zeros((q.shape[0], p.curves), np.int64)
         _check(lib().hco_positions(self.hi, self.lo, self.n, p.dim, p.perm, p.curves, p.dpc,
-                                   p.bits, q, q.shape[0], out), "positions")
+                                   p.bits, p.curve, q, q.shape[0], out), "positions")
         return out
 
     def candidates(self, queries, w):
@@ -168,7 +195,7 @@ class Index:
         counts = np.zeros(nq, np.uint32)
         ids = np.zeros((nq, max(stride, 1)), np.uint32)
         _check(lib().hco_candidates(self.hi, self.lo, self.ids, self.n, p.dim, p.perm,
-                                    p.curves, p.dpc, p.bits, q, nq, wv, counts, ids,
+                                    p.curves, p.dpc, p.bits, p.curve, q, nq, wv, counts, ids,
                                     max(stride, 1)), "candidates")
         return [ids[i, :counts[i]].copy() for i in range(nq)]
 
@@ -181,7 +208,8 @@ class Index:
         ids = np.zeros((nq, k), np.uint32)
         d = np.zeros((nq, k), np.uint32)
         _check(lib().hco_search(self.hi, self.lo, self.ids, self.db, self.n, p.dim, p.perm,
-                                p.curves, p.dpc, p.bits, q, nq, k, wv, ids, d), "search")
+                                p.curves, p.dpc, p.bits, p.curve, q, nq, k, wv, ids, d),
+               "search")
         return ids, d
 
     def labels(self, queries, k, truth_ids):
@@ -189,7 +217,8 @@ class Index:
         p = self.p
         out = np.zeros(q.shape[0], np.uint32)
         _check(lib().hco_labels(self.hi, self.lo, self.ids, self.n, p.dim, p.perm, p.curves,
-                                p.dpc, p.bits, q, q.shape[0], k, _c(truth_ids, np.uint32),
+                                p.dpc, p.bits, p.curve, q, q.shape[0], k,
+                                _c(truth_ids, np.uint32),
                                 out), "labels")
         return out
 
@@ -200,7 +229,8 @@ class Index:
         kv = np.broadcast_to(np.asarray(k, np.uint32), (nq,)).copy()
         out = np.zeros((nq, 24), np.float64)
         _check(lib().hco_features(self.hi, self.lo, self.ids, self.db, self.n, p.dim, p.perm,
-                                  p.curves, p.dpc, p.bits, q, nq, kv, out), "features")
+                                  p.curves, p.dpc, p.bits, p.curve, q, nq, kv, out),
+               "features")
         return out
 
 

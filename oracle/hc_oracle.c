@@ -16,7 +16,10 @@
  *                                 Butz-type scheme, here in the transposed
  *                                 form published by J. Skilling, "Programming
  *                                 the Hilbert curve", AIP Conf. Proc. 707, 2004)
- *   hco_keys                      Alg. 1 / Alg. 2 projection + key
+ *   hco_zorder_encode / _decode   the Z-order (Morton) key used as a comparison
+ *                                 curve (the space-filling curves of Sec. 2.2:
+ *                                 coordinate bits interleaved, no rotation)
+ *   hco_keys, hco_keys_ex         Alg. 1 / Alg. 2 projection + key
  *   hco_build                     Alg. 1 (sorted <key, id> list per curve)
  *   hco_lower_bound, hco_positions  binary search of the query key
  *   hco_candidates                Alg. 2 union of the per-curve windows
@@ -157,6 +160,36 @@ int hco_hilbert_decode(const uint64_t *hi, const uint64_t *lo, int64_t npts,
     return 0;
 }
 
+/* Z-order key: the coordinates' bits interleaved with no rotation or
+ * reflection (G. M. Morton, 1966), in the same bit layout as the Hilbert key:
+ * most significant level first, dim 0 first within a level.  It is the
+ * curve the Hilbert curve is compared with (Sec. 2.2): both visit every cell
+ * once, but only the Hilbert curve moves between adjacent cells. */
+int hco_zorder_encode(const uint32_t *coords, int64_t npts, int n, int bits,
+                      uint64_t *hi, uint64_t *lo)
+{
+    if (n < 1 || n > 128 || bits < 1 || bits > 32 || n * bits > 128)
+        return -1;
+    for (int64_t p = 0; p < npts; p++) {
+        u128 key = transposed_to_key(coords + p * n, n, bits);
+        hi[p] = (uint64_t)(key >> 64);
+        lo[p] = (uint64_t)key;
+    }
+    return 0;
+}
+
+int hco_zorder_decode(const uint64_t *hi, const uint64_t *lo, int64_t npts,
+                      int n, int bits, uint32_t *coords)
+{
+    if (n < 1 || n > 128 || bits < 1 || bits > 32 || n * bits > 128)
+        return -1;
+    for (int64_t p = 0; p < npts; p++) {
+        u128 key = ((u128)hi[p] << 64) | lo[p];
+        key_to_transposed(key, coords + p * n, n, bits);
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Projection + key of every row, every curve (Alg. 1 / Alg. 2)             */
 /* ------------------------------------------------------------------------ */
@@ -165,26 +198,35 @@ int hco_hilbert_decode(const uint64_t *hi, const uint64_t *lo, int64_t npts,
  * are 8-bit, so the curve is of order 8 (m-bit coordinates need an order-m
  * curve, Sec. 2.2.1) and a key holds dpc*8 bits. */
 static void row_keys(const uint8_t *row, const uint16_t *perm, int curves,
-                     int dpc, uint64_t *hi, uint64_t *lo)
+                     int dpc, int curve, uint64_t *hi, uint64_t *lo)
 {
     uint32_t proj[16];
     for (int c = 0; c < curves; c++) {
         for (int j = 0; j < dpc; j++)
             proj[j] = row[perm[c * dpc + j]];
-        hco_hilbert_encode(proj, 1, dpc, 8, &hi[c], &lo[c]);
+        if (curve == 1)
+            hco_zorder_encode(proj, 1, dpc, 8, &hi[c], &lo[c]);
+        else
+            hco_hilbert_encode(proj, 1, dpc, 8, &hi[c], &lo[c]);
     }
 }
 
-/* Output keys are laid out [row][curve]. */
-int hco_keys(const uint8_t *rows, int64_t nrows, int dim, const uint16_t *perm,
-             int curves, int dpc, int bits, uint64_t *hi, uint64_t *lo)
+/* Output keys are laid out [row][curve].  curve: 0 Hilbert, 1 Z-order. */
+int hco_keys_ex(const uint8_t *rows, int64_t nrows, int dim, const uint16_t *perm,
+                int curves, int dpc, int bits, int curve, uint64_t *hi, uint64_t *lo)
 {
-    if (bits != 8 || dpc < 1 || dpc > 16 || curves * dpc > dim)
+    if (bits != 8 || dpc < 1 || dpc > 16 || curves * dpc > dim || curve < 0 || curve > 1)
         return -1;
     #pragma omp parallel for schedule(static)
     for (int64_t r = 0; r < nrows; r++)
-        row_keys(rows + r * dim, perm, curves, dpc, hi + r * curves, lo + r * curves);
+        row_keys(rows + r * dim, perm, curves, dpc, curve, hi + r * curves, lo + r * curves);
     return 0;
+}
+
+int hco_keys(const uint8_t *rows, int64_t nrows, int dim, const uint16_t *perm,
+             int curves, int dpc, int bits, uint64_t *hi, uint64_t *lo)
+{
+    return hco_keys_ex(rows, nrows, dim, perm, curves, dpc, bits, 0, hi, lo);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -201,17 +243,17 @@ static int cmp_entry(const void *a, const void *b)
     return (x->id > y->id) - (x->id < y->id);
 }
 
-/* Output lists laid out [curve][n]. */
-int hco_build(const uint8_t *db, int64_t n, int dim, const uint16_t *perm,
-              int curves, int dpc, int bits,
-              uint64_t *shi, uint64_t *slo, uint32_t *sids)
+/* Output lists laid out [curve][n].  curve: 0 Hilbert, 1 Z-order. */
+int hco_build_ex(const uint8_t *db, int64_t n, int dim, const uint16_t *perm,
+                 int curves, int dpc, int bits, int curve,
+                 uint64_t *shi, uint64_t *slo, uint32_t *sids)
 {
-    if (bits != 8 || dpc < 1 || dpc > 16 || curves * dpc > dim)
+    if (bits != 8 || dpc < 1 || dpc > 16 || curves * dpc > dim || curve < 0 || curve > 1)
         return -1;
     uint64_t *khi = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n * curves + 1));
     uint64_t *klo = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n * curves + 1));
     if (!khi || !klo) { free(khi); free(klo); return -2; }
-    hco_keys(db, n, dim, perm, curves, dpc, bits, khi, klo);
+    hco_keys_ex(db, n, dim, perm, curves, dpc, bits, curve, khi, klo);
     int fail = 0;
     #pragma omp parallel for schedule(dynamic, 1)
     for (int c = 0; c < curves; c++) {
@@ -232,6 +274,13 @@ int hco_build(const uint8_t *db, int64_t n, int dim, const uint16_t *perm,
     free(khi);
     free(klo);
     return fail ? -2 : 0;
+}
+
+int hco_build(const uint8_t *db, int64_t n, int dim, const uint16_t *perm,
+              int curves, int dpc, int bits,
+              uint64_t *shi, uint64_t *slo, uint32_t *sids)
+{
+    return hco_build_ex(db, n, dim, perm, curves, dpc, bits, 0, shi, slo, sids);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -262,13 +311,14 @@ typedef struct {
     int64_t n;
     int dim, curves, dpc, bits;
     const uint16_t *perm;
+    int curve;                   /* 0 Hilbert, 1 Z-order */
 } oindex;
 
 static void query_positions(const oindex *ix, const uint8_t *q,
                             u128 *qkey, int64_t *pos)
 {
     uint64_t hi[64], lo[64];
-    row_keys(q, ix->perm, ix->curves, ix->dpc, hi, lo);
+    row_keys(q, ix->perm, ix->curves, ix->dpc, ix->curve, hi, lo);
     for (int c = 0; c < ix->curves; c++) {
         qkey[c] = ((u128)hi[c] << 64) | lo[c];
         pos[c] = hco_lower_bound(ix->shi + c * ix->n, ix->slo + c * ix->n,
@@ -277,11 +327,11 @@ static void query_positions(const oindex *ix, const uint8_t *q,
 }
 
 int hco_positions(const uint64_t *shi, const uint64_t *slo, int64_t n,
-                  int dim, const uint16_t *perm, int curves, int dpc, int bits,
+                  int dim, const uint16_t *perm, int curves, int dpc, int bits, int curve,
                   const uint8_t *queries, int64_t nq, int64_t *pos_out)
 {
     if (curves > 64) return -1;
-    oindex ix = { shi, slo, NULL, NULL, n, dim, curves, dpc, bits, perm };
+    oindex ix = { shi, slo, NULL, NULL, n, dim, curves, dpc, bits, perm, curve };
     #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t qi = 0; qi < nq; qi++) {
         u128 qkey[64];
@@ -323,11 +373,11 @@ static int64_t candidate_set(const oindex *ix, const int64_t *pos, int64_t w,
 /* counts[q] = |C_q|; ids[q*stride ...] = C_q ascending (stride >= 2*w_q*curves). */
 int hco_candidates(const uint64_t *shi, const uint64_t *slo, const uint32_t *sids,
                    int64_t n, int dim, const uint16_t *perm, int curves, int dpc,
-                   int bits, const uint8_t *queries, int64_t nq, const uint32_t *w,
+                   int bits, int curve, const uint8_t *queries, int64_t nq, const uint32_t *w,
                    uint32_t *counts, uint32_t *ids, int64_t stride)
 {
     if (curves > 64) return -1;
-    oindex ix = { shi, slo, sids, NULL, n, dim, curves, dpc, bits, perm };
+    oindex ix = { shi, slo, sids, NULL, n, dim, curves, dpc, bits, perm, curve };
     int bad = 0;
     #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t qi = 0; qi < nq; qi++) {
@@ -371,11 +421,12 @@ static int cmp_hit(const void *a, const void *b)
 /* Alg. 2: the k candidates closest to q, by (distance, id). */
 int hco_search(const uint64_t *shi, const uint64_t *slo, const uint32_t *sids,
                const uint8_t *db, int64_t n, int dim, const uint16_t *perm,
-               int curves, int dpc, int bits, const uint8_t *queries, int64_t nq,
-               int k, const uint32_t *w, uint32_t *out_ids, uint32_t *out_dists)
+               int curves, int dpc, int bits, int curve, const uint8_t *queries,
+               int64_t nq, int k, const uint32_t *w, uint32_t *out_ids,
+               uint32_t *out_dists)
 {
     if (curves > 64 || k < 1) return -1;
-    oindex ix = { shi, slo, sids, db, n, dim, curves, dpc, bits, perm };
+    oindex ix = { shi, slo, sids, db, n, dim, curves, dpc, bits, perm, curve };
     #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t qi = 0; qi < nq; qi++) {
         const uint8_t *q = queries + qi * dim;
@@ -441,7 +492,7 @@ int hco_brute_force(const uint8_t *db, int64_t n, int dim, const uint8_t *querie
 
 int hco_labels(const uint64_t *shi, const uint64_t *slo, const uint32_t *sids,
                int64_t n, int dim, const uint16_t *perm, int curves, int dpc,
-               int bits, const uint8_t *queries, int64_t nq, int k,
+               int bits, int curve, const uint8_t *queries, int64_t nq, int k,
                const uint32_t *truth_ids, uint32_t *labels)
 {
     if (curves > 64) return -1;
@@ -450,7 +501,7 @@ int hco_labels(const uint64_t *shi, const uint64_t *slo, const uint32_t *sids,
     for (int c = 0; c < curves; c++)
         for (int64_t r = 0; r < n; r++)
             rank[c * n + sids[c * n + r]] = (uint32_t)r;
-    oindex ix = { shi, slo, sids, NULL, n, dim, curves, dpc, bits, perm };
+    oindex ix = { shi, slo, sids, NULL, n, dim, curves, dpc, bits, perm, curve };
     #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t qi = 0; qi < nq; qi++) {
         u128 qkey[64];
@@ -498,13 +549,13 @@ static double lg1p128(u128 g)
 
 int hco_features(const uint64_t *shi, const uint64_t *slo, const uint32_t *sids,
                  const uint8_t *db, int64_t n, int dim, const uint16_t *perm,
-                 int curves, int dpc, int bits, const uint8_t *queries, int64_t nq,
-                 const uint32_t *k, double *feat)
+                 int curves, int dpc, int bits, int curve, const uint8_t *queries,
+                 int64_t nq, const uint32_t *k, double *feat)
 {
     if (curves != 8 || n < 1) return -1;
     static const int offs[6] = { -64, -8, -1, 1, 8, 64 };
     static const int spans[3] = { 1, 8, 64 };
-    oindex ix = { shi, slo, sids, db, n, dim, curves, dpc, bits, perm };
+    oindex ix = { shi, slo, sids, db, n, dim, curves, dpc, bits, perm, curve };
     #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t qi = 0; qi < nq; qi++) {
         const uint8_t *q = queries + qi * dim;
