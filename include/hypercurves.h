@@ -60,6 +60,12 @@ typedef enum {
 /* hipStream_t, passed opaquely; NULL is the null stream. */
 typedef void *hc_stream;
 
+/* Kinds of space-filling curve: the Hilbert curve of the method and, as a
+ * comparison, the Z-order curve, whose key intercalates the coordinates' bits
+ * (Sec. 2.2.1); both keys have the bit layout below. */
+#define HC_CURVE_HILBERT 0u
+#define HC_CURVE_ZORDER 1u
+
 /* Index parameters (Alg. 1 inputs `curves`, `dims[]`, `a`). */
 typedef struct {
     uint32_t dim;             /* vector dimension; must be 128 */
@@ -71,6 +77,9 @@ typedef struct {
                                  attribution a[c, j] of Alg. 1); each < dim.
                                  NULL = identity (curve c takes dims
                                  16c .. 16c+15).  Copied by the library. */
+    uint32_t curve;           /* HC_CURVE_HILBERT (0, the method's) or
+                                 HC_CURVE_ZORDER; keys of both kinds share the
+                                 bit layout below */
 } hc_params;
 
 typedef struct hc_index hc_index;   /* opaque host handle */
@@ -106,6 +115,27 @@ hc_status hc_build_index(const hc_params *p, const uint8_t *d_db, uint64_t n,
  * launched. */
 hc_status hc_index_attach(const hc_params *p, const uint8_t *d_db, uint64_t n,
                           void *d_index, size_t index_bytes, hc_index **out);
+
+/* Rows appended to the database, inserted without a rebuild (Alg. 1 may run
+ * incrementally, Sec. 3.1, and the index builder/updater pipeline adds
+ * arriving vectors to a live index, Sec. 4.1; Alg. 1 defines the lists that
+ * result).  d_db holds n + m rows whose first n are the
+ * rows idx was built over (the buffer may be a new one); rows n .. n + m - 1
+ * are inserted.  The new index goes to d_index (hc_insert_bytes: at least
+ * index_bytes, 256-byte aligned, not overlapping idx's buffer); idx and its
+ * buffer are only read and stay valid.  Per curve, the appended rows' keys are
+ * sorted by (key, id) and merged with the old list (every appended id is
+ * larger than every old one, so at an equal key the old entry comes first),
+ * then the sampled-key table is rebuilt: the result equals hc_build_index
+ * over all n + m rows, bit for bit.  Scratch: hc_insert_bytes' scratch_bytes,
+ * 256-byte aligned.  Synchronises the stream once per curve.  Errors: null
+ * or misaligned pointers, m = 0, overlapping buffers -> HC_ERR_INVALID;
+ * n + m >= 2^32 - 1 -> HC_ERR_UNSUPPORTED; small buffers -> HC_ERR_SIZE. */
+hc_status hc_insert_bytes(const hc_index *idx, uint64_t m, size_t *index_bytes,
+                          size_t *scratch_bytes);
+hc_status hc_insert_rows(const hc_index *idx, const uint8_t *d_db, uint64_t m, void *d_index,
+                         size_t index_bytes, void *d_scratch, size_t scratch_bytes,
+                         hc_stream stream, hc_index **out);
 
 /* Frees the host handle only (the caller owns every device buffer). */
 hc_status hc_index_destroy(hc_index *idx);

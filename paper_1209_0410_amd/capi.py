@@ -29,7 +29,7 @@ class hc_uneven_cfg(ct.Structure):
 class hc_params(ct.Structure):
     _fields_ = [("dim", ct.c_uint32), ("curves", ct.c_uint32),
                 ("dims_per_curve", ct.c_uint32), ("bits", ct.c_uint32),
-                ("perm", ct.POINTER(ct.c_uint16))]
+                ("perm", ct.POINTER(ct.c_uint16)), ("curve", ct.c_uint32)]
 
 
 _vp = ct.c_void_p
@@ -43,6 +43,8 @@ SIGNATURES = {
     "hc_index_bytes": [_pp, _u64, ct.POINTER(_sz), ct.POINTER(_sz)],
     "hc_build_index": [_pp, _vp, _u64, _vp, _sz, _vp, _sz, _vp, ct.POINTER(_vp)],
     "hc_index_attach": [_pp, _vp, _u64, _vp, _sz, ct.POINTER(_vp)],
+    "hc_insert_bytes": [_vp, _u64, ct.POINTER(_sz), ct.POINTER(_sz)],
+    "hc_insert_rows": [_vp, _vp, _u64, _vp, _sz, _vp, _sz, _vp, ct.POINTER(_vp)],
     "hc_index_destroy": [_vp],
     "hc_index_curve": [_vp, _u32, ct.POINTER(_vp), ct.POINTER(_vp)],
     "hc_index_info": [_vp, ct.POINTER(_u64), ct.POINTER(_u32)],
@@ -107,9 +109,12 @@ def call(name, *args):
     return rc
 
 
-def make_params(dim=128, curves=8, dims_per_curve=16, bits=8, perm=None):
+CURVES = {"hilbert": 0, "zorder": 1}     # HC_CURVE_HILBERT, HC_CURVE_ZORDER
+
+
+def make_params(dim=128, curves=8, dims_per_curve=16, bits=8, perm=None, curve="hilbert"):
     """hc_params plus the ctypes array that keeps `perm` alive."""
-    p = hc_params(dim, curves, dims_per_curve, bits, None)
+    p = hc_params(dim, curves, dims_per_curve, bits, None, CURVES[curve])
     keep = None
     if perm is not None:
         keep = (ct.c_uint16 * len(perm))(*[int(x) for x in perm])

@@ -7,6 +7,11 @@
 // every key (common: the data are small, so many high-order Hilbert bits are
 // zero) is skipped.  Finally the 64-ary sampled-key table the search descends
 // is extracted: level L holds key[j * 64^L].
+//
+// Rows appended to the database are inserted without a rebuild: their keys
+// are sorted the same way and merged with each existing list (every new id is
+// larger than every old one, so at an equal key the old entry comes first);
+// the result is the index a full build over all rows gives, bit for bit.
 #include <string.h>
 
 #include <new>
@@ -39,16 +44,18 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, uint64_t n, uint3
         p[i] = v;
 }
 
-// Keys of curve c for every row, ids ascending.
-__global__ __launch_bounds__(256) void k_encode_curve(IndexView v, uint32_t c, Key *keys,
+// Keys of curve c for rows[0, count), ids id_base + i (ascending).
+__global__ __launch_bounds__(256) void k_encode_curve(IndexView v, uint32_t c,
+                                                      const uint8_t *rows, uint64_t count,
+                                                      uint32_t id_base, Key *keys,
                                                       uint32_t *ids)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= v.n) return;
+    if (i >= count) return;
     uint32_t coord[kDpc];
-    project16(v.db + i * kDim, v, c, coord);
-    keys[i] = hilbert_key16(coord);
-    ids[i] = (uint32_t)i;
+    project16(rows + i * kDim, v, c, coord);
+    keys[i] = curve_key16(coord, v.curve);
+    ids[i] = id_base + (uint32_t)i;
 }
 
 // Histograms of all sixteen digits (hist[d * 256 + value]).
@@ -143,6 +150,45 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const Key *src, const 
     }
 }
 
+// Merge of an existing list (old, n entries) with the sorted entries of
+// appended rows (add, m entries) into out (n + m).  An appended entry goes
+// after every old entry whose key is <= its key; an old entry goes after
+// every appended entry whose key is < its key.
+__global__ __launch_bounds__(256) void k_merge_added(const Key *old_keys, uint64_t n,
+                                                     const Key *add_keys,
+                                                     const uint32_t *add_ids, uint64_t m,
+                                                     Key *out_keys, uint32_t *out_ids)
+{
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const Key x = add_keys[j];
+    uint64_t a = 0, b = n;
+    while (a < b) {
+        const uint64_t mid = a + (b - a) / 2;
+        if (key_less(x, old_keys[mid])) b = mid;
+        else a = mid + 1;
+    }
+    out_keys[a + j] = x;
+    out_ids[a + j] = add_ids[j];
+}
+
+__global__ __launch_bounds__(256) void k_merge_old(const Key *old_keys, const uint32_t *old_ids,
+                                                   uint64_t n, const Key *add_keys, uint64_t m,
+                                                   Key *out_keys, uint32_t *out_ids)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Key x = old_keys[i];
+    uint64_t a = 0, b = m;
+    while (a < b) {
+        const uint64_t mid = a + (b - a) / 2;
+        if (key_less(add_keys[mid], x)) a = mid + 1;
+        else b = mid;
+    }
+    out_keys[i + a] = x;
+    out_ids[i + a] = old_ids[i];
+}
+
 // Level L of the sampled-key table: out[j] = leaf[j * stride].
 __global__ __launch_bounds__(256) void k_sample_keys(const Key *leaf, uint64_t stride,
                                                      Key *out, uint64_t len)
@@ -181,13 +227,12 @@ static uint32_t blocks_for(uint64_t n, uint32_t per)
     return (uint32_t)((n + per - 1) / per);
 }
 
-static hc_status sort_curve(const IndexView &v, uint32_t c, Key *keys, uint32_t *ids,
-                            const BuildScratch &s, hipStream_t st)
+// Stable LSD radix sort of (keys, ids) by key, in place (s holds the second
+// buffer).  Synchronises the stream once, to read the digit histograms.
+static hc_status radix_sort(Key *keys, uint32_t *ids, uint64_t n, const BuildScratch &s,
+                            hipStream_t st)
 {
-    const uint64_t n = v.n;
     const uint32_t ntiles = blocks_for(n, kSortTile);
-    hipLaunchKernelGGL(k_encode_curve, dim3(blocks_for(n, 256)), dim3(256), 0, st, v, c,
-                       keys, ids);
     hipLaunchKernelGGL(k_fill_u32, dim3(16), dim3(256), 0, st, s.hist, (uint64_t)16 * 256,
                        0u);
     const uint32_t hblocks = (uint32_t)std::min<uint64_t>(1024, blocks_for(n, 256));
@@ -221,13 +266,65 @@ static hc_status sort_curve(const IndexView &v, uint32_t c, Key *keys, uint32_t 
                            st) != hipSuccess)
             return HC_ERR_HIP;
     }
+    return last_hip();
+}
+
+// The sampled-key levels of curve c from its sorted keys.
+static hc_status sample_levels(const IndexView &v, uint32_t c, hipStream_t st)
+{
     uint64_t stride = 1;
     for (uint32_t l = 1; l <= v.levels; l++) {
         stride *= kFan;
         hipLaunchKernelGGL(k_sample_keys, dim3(blocks_for(v.len[l], 256)), dim3(256), 0, st,
-                           (const Key *)keys, stride, (Key *)v.lvl[c][l], v.len[l]);
+                           v.lvl[c][0], stride, (Key *)v.lvl[c][l], v.len[l]);
     }
     return last_hip();
+}
+
+static hc_status sort_curve(const IndexView &v, uint32_t c, Key *keys, uint32_t *ids,
+                            const BuildScratch &s, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_encode_curve, dim3(blocks_for(v.n, 256)), dim3(256), 0, st, v, c,
+                       v.db, v.n, 0u, keys, ids);
+    hc_status r = radix_sort(keys, ids, v.n, s, st);
+    if (r != HC_OK) return r;
+    return sample_levels(v, c, st);
+}
+
+// Scratch of an insertion of m rows: the appended entries (keys, ids) and a
+// radix-sort scratch for m keys.
+struct InsertScratch {
+    Key *keys;
+    uint32_t *ids;
+    BuildScratch sort;
+    size_t total;
+};
+
+static InsertScratch insert_scratch_layout(uint64_t m, uint8_t *base)
+{
+    InsertScratch s{};
+    size_t off = 0;
+    s.keys = (Key *)(base + off);
+    off = align256(off + sizeof(Key) * m);
+    s.ids = (uint32_t *)(base + off);
+    off = align256(off + sizeof(uint32_t) * m);
+    s.sort = build_scratch_layout(m, base ? base + off : nullptr);
+    s.total = off + s.sort.total;
+    return s;
+}
+
+// Parameters of an existing index, for a new view of the same kind.
+static hc_params params_of(const IndexView &v)
+{
+    hc_params p;
+    memset(&p, 0, sizeof(p));
+    p.dim = kDim;
+    p.curves = v.curves;
+    p.dims_per_curve = kDpc;
+    p.bits = 8;
+    p.perm = v.perm;
+    p.curve = v.curve;
+    return p;
 }
 
 }  // namespace hc
@@ -245,6 +342,61 @@ hc_status hc_index_bytes(const hc_params *p, uint64_t n, size_t *index_bytes,
     if (n >= 0xFFFFFFFFull) return HC_ERR_UNSUPPORTED;
     if (index_bytes) *index_bytes = make_layout(p->curves, n).total;
     if (build_scratch_bytes) *build_scratch_bytes = build_scratch_layout(n, nullptr).total;
+    return HC_OK;
+}
+
+hc_status hc_insert_bytes(const hc_index *idx, uint64_t m, size_t *index_bytes,
+                          size_t *scratch_bytes)
+{
+    if (!idx || m == 0) return HC_ERR_INVALID;
+    const uint64_t n = idx->v.n + m;
+    if (n < m || n >= 0xFFFFFFFFull) return HC_ERR_UNSUPPORTED;
+    if (index_bytes) *index_bytes = make_layout(idx->v.curves, n).total;
+    if (scratch_bytes) *scratch_bytes = insert_scratch_layout(m, nullptr).total;
+    return HC_OK;
+}
+
+hc_status hc_insert_rows(const hc_index *idx, const uint8_t *d_db, uint64_t m, void *d_index,
+                         size_t index_bytes, void *d_scratch, size_t scratch_bytes,
+                         hc_stream stream, hc_index **out)
+{
+    if (!idx || !out || m == 0 || !d_scratch || ((uintptr_t)d_scratch & 255))
+        return HC_ERR_INVALID;
+    const uint64_t n0 = idx->v.n, n = n0 + m;
+    if (n < m || n >= 0xFFFFFFFFull) return HC_ERR_UNSUPPORTED;
+    // the new index is written next to the old one, never over it
+    const uintptr_t a0 = (uintptr_t)idx->base, a1 = a0 + idx->bytes;
+    const uintptr_t b0 = (uintptr_t)d_index, b1 = b0 + index_bytes;
+    if (d_index && b0 < a1 && a0 < b1) return HC_ERR_INVALID;
+    const InsertScratch s = insert_scratch_layout(m, (uint8_t *)d_scratch);
+    if (scratch_bytes < s.total) return HC_ERR_SIZE;
+    hc_index *h = new (std::nothrow) hc_index;
+    if (!h) return HC_ERR_INVALID;
+    const hc_params p = params_of(idx->v);
+    hc_status st = fill_view(&p, d_db, n, d_index, index_bytes, &h->v);
+    const hipStream_t hs = (hipStream_t)stream;
+    for (uint32_t c = 0; st == HC_OK && c < h->v.curves; c++) {
+        hipLaunchKernelGGL(k_encode_curve, dim3(blocks_for(m, 256)), dim3(256), 0, hs, h->v,
+                           c, d_db + n0 * kDim, m, (uint32_t)n0, s.keys, s.ids);
+        st = radix_sort(s.keys, s.ids, m, s.sort, hs);
+        if (st != HC_OK) break;
+        Key *keys = (Key *)h->v.lvl[c][0];
+        uint32_t *ids = (uint32_t *)h->v.ids[c];
+        hipLaunchKernelGGL(k_merge_old, dim3(blocks_for(n0, 256)), dim3(256), 0, hs,
+                           idx->v.lvl[c][0], idx->v.ids[c], n0, (const Key *)s.keys, m, keys,
+                           ids);
+        hipLaunchKernelGGL(k_merge_added, dim3(blocks_for(m, 256)), dim3(256), 0, hs,
+                           idx->v.lvl[c][0], n0, (const Key *)s.keys, (const uint32_t *)s.ids,
+                           m, keys, ids);
+        st = sample_levels(h->v, c, hs);
+    }
+    if (st != HC_OK) {
+        delete h;
+        return st;
+    }
+    h->base = d_index;
+    h->bytes = index_bytes;
+    *out = h;
     return HC_OK;
 }
 

@@ -14,6 +14,7 @@ hc_status check_params(const hc_params *p, uint16_t *perm_out, uint32_t *identit
     if (p->dim != (uint32_t)kDim || p->dims_per_curve != (uint32_t)kDpc || p->bits != 8)
         return HC_ERR_UNSUPPORTED;
     if (p->curves < 1 || p->curves > (uint32_t)kMaxCurves) return HC_ERR_UNSUPPORTED;
+    if (p->curve != HC_CURVE_HILBERT && p->curve != HC_CURVE_ZORDER) return HC_ERR_UNSUPPORTED;
     uint32_t ident = 1;
     for (uint32_t i = 0; i < p->curves * kDpc; i++) {
         uint16_t d = p->perm ? p->perm[i] : (uint16_t)i;
@@ -39,6 +40,7 @@ hc_status fill_view(const hc_params *p, const uint8_t *d_db, uint64_t n, void *d
     v->db = d_db;
     v->n = n;
     v->curves = p->curves;
+    v->curve = p->curve;
     v->levels = L.levels;
     for (uint32_t l = 0; l <= L.levels; l++) v->len[l] = L.len[l];
     uint8_t *base = (uint8_t *)d_index;
@@ -60,7 +62,7 @@ __global__ __launch_bounds__(256) void k_encode_rows(IndexView v, const uint8_t 
     const uint32_t c = (uint32_t)(t - r * v.curves);
     uint32_t coord[kDpc];
     project16(rows + r * kDim, v, c, coord);
-    keys[t] = hilbert_key16(coord);
+    keys[t] = curve_key16(coord, v.curve);
 }
 
 hc_status encode_rows(const IndexView &v, const uint8_t *rows, uint64_t nrows, Key *keys,
@@ -104,6 +106,7 @@ hc_status hc_encode_keys(const hc_params *p, const uint8_t *d_rows, uint64_t nro
         return HC_ERR_INVALID;
     if (nrows > (1ull << 40)) return HC_ERR_UNSUPPORTED;
     v.curves = p->curves;
+    v.curve = p->curve;
     return encode_rows(v, d_rows, nrows, (Key *)d_keys, (hipStream_t)stream);
 }
 

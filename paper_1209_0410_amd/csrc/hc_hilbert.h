@@ -1,4 +1,5 @@
-// Hilbert extended key of a 16-dim point with 8-bit coordinates (gfx950).
+// Extended keys of a 16-dim point with 8-bit coordinates (gfx950): the
+// Hilbert key of the method and, for comparison, the Z-order key.
 //
 // The curve is the Butz-type Hilbert curve the paper uses (Sec. 2.2.1), in the
 // transposed form of J. Skilling ("Programming the Hilbert curve", AIP Conf.
@@ -36,6 +37,25 @@ __device__ inline uint64_t spread_bytes(uint32_t v)
     return x;
 }
 
+// Bit-plane transpose of 16 8-bit values into a key: level 7 of dims 0..15,
+// then level 6, and so on.  Dims 0..7 and 8..15 are transposed as two 8x8 bit
+// matrices whose rows are interleaved byte by byte.
+__device__ inline Key interleave_key16(const uint32_t (&x)[kDpc])
+{
+    uint64_t a = 0, b = 0;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        a |= (uint64_t)(x[i] & 0xFFu) << (56 - 8 * i);
+        b |= (uint64_t)(x[i + 8] & 0xFFu) << (56 - 8 * i);
+    }
+    a = transpose8x8(a);   // byte r: level 7-r of dims 0..7
+    b = transpose8x8(b);   // byte r: level 7-r of dims 8..15
+    Key k;
+    k.hi = (spread_bytes((uint32_t)(a >> 32)) << 8) | spread_bytes((uint32_t)(b >> 32));
+    k.lo = (spread_bytes((uint32_t)a) << 8) | spread_bytes((uint32_t)b);
+    return k;
+}
+
 __device__ inline Key hilbert_key16(const uint32_t (&coord)[kDpc])
 {
     uint32_t x[kDpc];
@@ -69,21 +89,19 @@ __device__ inline Key hilbert_key16(const uint32_t (&coord)[kDpc])
 #pragma unroll
     for (int i = 0; i < kDpc; i++) x[i] ^= par;
 
-    // Bit-plane transpose: the key lists level 7 of dims 0..15, then level 6,
-    // and so on.  Dims 0..7 and 8..15 are transposed as two 8x8 bit matrices
-    // whose rows are interleaved byte by byte.
-    uint64_t a = 0, b = 0;
-#pragma unroll
-    for (int i = 0; i < 8; i++) {
-        a |= (uint64_t)(x[i] & 0xFFu) << (56 - 8 * i);
-        b |= (uint64_t)(x[i + 8] & 0xFFu) << (56 - 8 * i);
-    }
-    a = transpose8x8(a);   // byte r: level 7-r of dims 0..7
-    b = transpose8x8(b);   // byte r: level 7-r of dims 8..15
-    Key k;
-    k.hi = (spread_bytes((uint32_t)(a >> 32)) << 8) | spread_bytes((uint32_t)(b >> 32));
-    k.lo = (spread_bytes((uint32_t)a) << 8) | spread_bytes((uint32_t)b);
-    return k;
+    return interleave_key16(x);
+}
+
+// Z-order (Morton) key: the coordinates' bits interleaved as they are, with
+// no Hilbert rotation.
+__device__ inline Key zorder_key16(const uint32_t (&coord)[kDpc])
+{
+    return interleave_key16(coord);
+}
+
+__device__ inline Key curve_key16(const uint32_t (&coord)[kDpc], uint32_t curve)
+{
+    return curve == HC_CURVE_ZORDER ? zorder_key16(coord) : hilbert_key16(coord);
 }
 
 // Loads the 16 coordinates of curve c of a 128-byte row.

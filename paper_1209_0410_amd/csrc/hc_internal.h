@@ -31,6 +31,7 @@ struct IndexView {
     const uint32_t *ids[kMaxCurves];
     uint16_t perm[kMaxCurves * kDpc];
     uint32_t identity;                        // perm is 16c + j
+    uint32_t curve;                           // HC_CURVE_HILBERT or HC_CURVE_ZORDER
 };
 
 }  // namespace hc

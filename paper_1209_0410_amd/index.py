@@ -32,10 +32,11 @@ def _empty_bytes(nbytes, device):
     return t[off:off + max(int(nbytes), 256)]
 
 
-def encode_keys(rows, curves=8, perm=None):
-    """Hilbert keys of every row and curve: int64 tensor (rows, curves, 2) of {hi, lo}."""
+def encode_keys(rows, curves=8, perm=None, curve="hilbert"):
+    """Keys (Hilbert, or Z-order) of every row and curve: int64 tensor
+    (rows, curves, 2) of {hi, lo}."""
     _check_rows(rows, "rows")
-    p, keep = capi.make_params(curves=curves, perm=perm)
+    p, keep = capi.make_params(curves=curves, perm=perm, curve=curve)
     out = torch.empty((rows.shape[0], curves, 2), dtype=torch.int64, device=rows.device)
     capi.call("hc_encode_keys", ct.byref(p), _ptr(rows), rows.shape[0], _ptr(out), _stream())
     del keep
@@ -43,15 +44,17 @@ def encode_keys(rows, curves=8, perm=None):
 
 
 class Index:
-    """Alg. 1 index of a resident uint8 database (n, 128) on one GPU."""
+    """Alg. 1 index of a resident uint8 database (n, 128) on one GPU.  `curve`:
+    "hilbert" (the method's) or "zorder" (for comparison)."""
 
-    def __init__(self, db, curves=8, perm=None):
+    def __init__(self, db, curves=8, perm=None, curve="hilbert"):
         _check_rows(db, "db")
         self.db = db
         self.n = db.shape[0]
         self.curves = curves
+        self.curve_kind = curve
         self.perm = None if perm is None else [int(x) for x in perm]
-        self._p, self._keep = capi.make_params(curves=curves, perm=self.perm)
+        self._p, self._keep = capi.make_params(curves=curves, perm=self.perm, curve=curve)
         ib, sb = ct.c_size_t(), ct.c_size_t()
         capi.call("hc_index_bytes", ct.byref(self._p), self.n, ct.byref(ib), ct.byref(sb))
         self.index_bytes = ib.value
@@ -66,13 +69,14 @@ class Index:
         del scratch
 
     @classmethod
-    def attach(cls, db, buf, curves=8, perm=None):
+    def attach(cls, db, buf, curves=8, perm=None, curve="hilbert"):
         """Handle over an index buffer restored from a previous build."""
         self = cls.__new__(cls)
         _check_rows(db, "db")
         self.db, self.n, self.curves = db, db.shape[0], curves
+        self.curve_kind = curve
         self.perm = None if perm is None else [int(x) for x in perm]
-        self._p, self._keep = capi.make_params(curves=curves, perm=self.perm)
+        self._p, self._keep = capi.make_params(curves=curves, perm=self.perm, curve=curve)
         self.buf = buf
         self.index_bytes = buf.numel()
         h = ct.c_void_p()
@@ -81,6 +85,33 @@ class Index:
         self.handle = h
         self._scratch = None
         return self
+
+    def insert(self, db):
+        """Index over `db`, whose first n rows are this index's rows, made by
+        inserting rows n .. (no rebuild); equal to Index(db) bit for bit.  This
+        index stays valid."""
+        _check_rows(db, "db")
+        m = db.shape[0] - self.n
+        if m < 1:
+            raise ValueError("db must hold more rows than the index")
+        ib, sb = ct.c_size_t(), ct.c_size_t()
+        capi.call("hc_insert_bytes", self.handle, m, ct.byref(ib), ct.byref(sb))
+        new = Index.__new__(Index)
+        new.db, new.n, new.curves = db, db.shape[0], self.curves
+        new.curve_kind, new.perm = self.curve_kind, self.perm
+        new._p, new._keep = capi.make_params(curves=self.curves, perm=self.perm,
+                                             curve=self.curve_kind)
+        new.index_bytes = ib.value
+        new.buf = _empty_bytes(ib.value, db.device)
+        scratch = _empty_bytes(sb.value, db.device)
+        h = ct.c_void_p()
+        capi.call("hc_insert_rows", self.handle, _ptr(db), m, _ptr(new.buf), ib.value,
+                  _ptr(scratch), sb.value, _stream(), ct.byref(h))
+        new.handle = h
+        new._scratch = None
+        torch.cuda.current_stream().synchronize()
+        del scratch
+        return new
 
     def __del__(self):
         h = getattr(self, "handle", None)

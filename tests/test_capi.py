@@ -58,6 +58,10 @@ def test_index_bytes_validation(lib):
     assert lib.hc_index_bytes(ct.byref(bad), 10, ct.byref(ib), None) == capi.HC_ERR_UNSUPPORTED
     bad, keep = capi.make_params(perm=[200] * 128)
     assert lib.hc_index_bytes(ct.byref(bad), 10, ct.byref(ib), None) == capi.HC_ERR_INVALID
+    z, _ = capi.make_params(curve="zorder")
+    assert lib.hc_index_bytes(ct.byref(z), 10, ct.byref(ib), None) == 0
+    z.curve = 2
+    assert lib.hc_index_bytes(ct.byref(z), 10, ct.byref(ib), None) == capi.HC_ERR_UNSUPPORTED
 
 
 def test_search_rejects_bad_arguments_before_launch(lib):

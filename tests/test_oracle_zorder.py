@@ -1,6 +1,6 @@
-"""Pins of the oracle's Z-order key, the comparison curve of the space-filling
-curves the paper surveys (Sec. 2.2), against what defines a Z-order (Morton)
-curve rather than the oracle's own bit loop:
+"""Pins of the oracle's Z-order key (the comparison curve of Sec. 2.2.1, whose
+key intercalates the coordinates' bits) against what defines a Z-order
+(Morton) curve rather than the oracle's own bit loop:
 
 - the key is a bijection from the d-dim grid of m-bit coordinates onto the
   d*m-bit keys;
