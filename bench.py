@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--w-max", type=int, default=1 << 17)
     ap.add_argument("--latency-batch", type=int, default=1000)
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--f4", type=int, default=1,
+                    help="Z-order comparison and incremental insertion (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--w-fixed", type=int, default=0,
                     help="use this fixed w instead of calibrating it (profiling runs)")
@@ -220,6 +222,8 @@ def main():
         learned_row.pop("_model", None)
 
     uneven = run_uneven(a, ix, rank, gdb, dev) if a.uneven else None
+    f4 = run_f4(a, ix, gdb, gq, gcq, ctruth, out, timed, recall_of, w_fix, build_s,
+                dev) if a.f4 else None
 
     cpu = None
     if a.cpu_baseline:
@@ -255,6 +259,7 @@ def main():
         "build_s": build_s,
         "sweep": rows,
         "uneven": uneven,
+        "f4": f4,
         "roofline": roofline(head),
     }
     if head is fixed:
@@ -375,6 +380,54 @@ def counted_traffic(n, nq, k, w, path):
             if line.startswith("traffic_bytes_per_launch:"):
                 return float(line.split(":")[1]), os.path.relpath(path, ROOT)
     return None, None
+
+
+def run_f4(a, ix, gdb, gq, gcq, ctruth, out, timed, recall_of, w_fix, build_s, dev):
+    """The Z-order curve in place of the Hilbert curve (same data, same
+    calibration), and rows appended to a built index without a rebuild."""
+    import torch
+    from paper_1209_0410_amd import learned
+    from paper_1209_0410_amd.index import Index
+    k = a.k
+    zx = Index(gdb, curve="zorder")
+    zsc = zx.scratch(a.nq)
+    rec_h_w = None
+
+    def step(w):
+        def fn(ev=None, st=None):
+            if ev is not None:
+                ev[0].record(st)
+                ev[1].record(st)
+            zx.search(gq, k, w, out=out, scratch=zsc)
+            if ev is not None:
+                ev[2].record(st)
+        return fn
+
+    timed(step(w_fix), 1, 1)
+    rec_h_w = recall_of(out[0])
+    w_z, rec_c = learned.calibrate_fixed_w(zx, gcq, ctruth, k, CALIB_TARGET, hi=1 << 20)
+    zs, zk, _ = timed(step(w_z), a.steps, a.warmup)
+    z = dict(recall_at_hilbert_w=rec_h_w, hilbert_w=w_fix, w=w_z, calib_recall=rec_c,
+             step_ms=zs, qps=a.nq / zs * 1e3, recall=recall_of(out[0]))
+    log(f"z-order: recall {rec_h_w:.4f} at the Hilbert w={w_fix}; needs w={w_z} for "
+        f"{CALIB_TARGET}: {zs:.3f} ms/step, {z['qps']:.3e} q/s, recall {z['recall']:.4f}")
+    del zx, zsc
+    # insertion: the last 1% of the rows appended to an index over the rest
+    m = max(1, a.n // 100)
+    base = Index(gdb[:a.n - m])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ins = base.insert(gdb)
+    torch.cuda.synchronize()
+    ins_s = time.perf_counter() - t0
+    same = all(torch.equal(ins.curve(c)[0], ix.curve(c)[0]) and
+               torch.equal(ins.curve(c)[1], ix.curve(c)[1]) for c in range(8))
+    ins_row = dict(n0=a.n - m, m=m, insert_s=ins_s, full_build_s=build_s,
+                   equals_full_build=bool(same))
+    log(f"insert {m} rows into {a.n - m}: {ins_s:.3f}s (full build {build_s:.3f}s), "
+        f"equal to the full build: {same}")
+    del base, ins
+    return {"zorder": z, "insert": ins_row}
 
 
 def run_uneven(a, ix, rank, gdb, dev):
