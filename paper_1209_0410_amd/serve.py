@@ -11,8 +11,11 @@ decided at run time), with slots on streams in place of its CPU/GPU buffers.
 The arrival process is seeded: Poisson with a rate that varies sinusoidally,
 drawn by thinning (Lewis & Shedler).
 """
+import argparse
 import collections
+import json
 import math
+import sys
 import time
 
 import numpy as np
@@ -138,6 +141,8 @@ class Server:
         sizes = []
         t0 = time.perf_counter()
         clock = (lambda: time.perf_counter() - t0) if realtime else None
+        arrivals = np.asarray(arrivals, np.float64)
+        next_log = 5.0
         while nxt < R or inflight:
             now = clock() if realtime else math.inf
             # retire finished batches (oldest first; each slot records one event)
@@ -154,10 +159,12 @@ class Server:
                     res_d[lo:hi] = slot.host_dists[:hi - lo].numpy().view(np.uint32)
                 slot.busy = False
                 self.budget.give(nb)
+            if log is not None and realtime and now >= next_log:
+                log(f"t={now:.1f}s: {nxt} of {R} admitted, {len(inflight)} batches in flight")
+                next_log += 5.0
             # admit what has arrived into a free slot, as much as the budget allows
-            ready_end = nxt
-            while ready_end < R and arrivals[ready_end] <= now and ready_end - nxt < self.max_batch:
-                ready_end += 1
+            arrived = R if not realtime else int(np.searchsorted(arrivals, now, side="right"))
+            ready_end = min(arrived, nxt + self.max_batch)
             free = [s for s in self.slots if not s.busy]
             if ready_end > nxt and free:
                 per = batch_bytes(1, self.k_stride)
@@ -207,3 +214,101 @@ def stream_of(s):
 def _cfgp(cfg):
     import ctypes as ct
     return ct.byref(cfg) if cfg is not None else None
+
+
+def main(argv=None):
+    """The serving scenario: a resident index over n rows, requests arriving at
+    a rate that moves sinusoidally between lo and hi per second, k drawn from
+    {1, 10, 100}, w per request from the learned model (fixed w as its
+    fallback).  Prints one JSON line: latency p50/p99, sustained queries/s,
+    batching, and recall@min(k, 10) of the learned and the fixed w on a sample
+    of the requests (each searched again alone: results do not depend on the
+    mix)."""
+    from . import datagen
+    from .index import Index, brute_force
+    ap = argparse.ArgumentParser(prog="python -m paper_1209_0410_amd.serve")
+    ap.add_argument("--n", type=int, default=100_000_000)
+    ap.add_argument("--duration", type=float, default=60.0)
+    ap.add_argument("--lo", type=float, default=1_000.0)
+    ap.add_argument("--hi", type=float, default=200_000.0)
+    ap.add_argument("--period", type=float, default=60.0)
+    ap.add_argument("--w", type=int, default=16, help="fixed w (the fallback)")
+    ap.add_argument("--w-max", type=int, default=64, help="largest learned w")
+    ap.add_argument("--train", type=int, default=100_000)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--slots", type=int, default=3)
+    ap.add_argument("--max-batch", type=int, default=16_384)
+    ap.add_argument("--recall-sample", type=int, default=2_000)
+    a = ap.parse_args(argv)
+
+    def log(msg):
+        print(f"[serve] {msg}", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    db = datagen.make_db(a.n)
+    gdb = torch.from_numpy(db).to(dev)
+    del db
+    ix = Index(gdb)
+    torch.cuda.synchronize()
+    log(f"{a.n} rows resident, index {ix.index_bytes / 1e9:.1f} GB, {time.time() - t0:.1f}s")
+
+    # learned w: labels from exact kNN, the model trained on the GPU; delta is
+    # set so that the mean learned w equals the fixed w (equal search cost)
+    t0 = time.time()
+    rank = learned.ranks(ix)
+    tq = torch.from_numpy(datagen.make_queries(a.train, seed=datagen.SEED_TRAIN)).to(dev)
+    ttruth, _ = brute_force(gdb, tq, 10)
+    lab = learned.labels(ix, rank, tq, ttruth)
+    feats = learned.features(ix, tq, 10)
+    model = learned.WModel(dev, seed=0, w_min=8, w_max=a.w_max)
+    model.set_norm(feats)
+    model.train(feats, model.targets(lab), epochs=a.epochs, batch=4096, lr=1e-3, seed=1)
+    cq = torch.from_numpy(datagen.make_queries(10_000, seed=datagen.SEED_CALIB)).to(dev)
+    cf = learned.features(ix, cq, 10)
+    lo_d, hi_d = -16.0, 16.0
+    for _ in range(40):
+        mid = 0.5 * (lo_d + hi_d)
+        if model.windows(cf, mid, a.w).float().mean().item() > a.w:
+            hi_d = mid
+        else:
+            lo_d = mid
+    model.delta = lo_d
+    del rank, tq, ttruth, lab, feats
+    torch.cuda.synchronize()
+    log(f"model trained on {a.train} queries, delta {model.delta:.3f}, {time.time() - t0:.1f}s")
+
+    arrivals = sinusoidal_arrivals(a.duration, a.lo, a.hi, a.period, seed=datagen.SEED_ARRIVALS)
+    R = len(arrivals)
+    queries = datagen.make_queries(R, seed=datagen.SEED_EVAL)
+    ks = np.random.default_rng(datagen.SEED_ARRIVALS).choice(
+        np.array([1, 10, 100], np.uint32), size=R)
+    log(f"{R} requests over {a.duration:.0f}s, rate {a.lo:.0f} .. {a.hi:.0f} per s")
+    srv = Server(ix, model=model, w_fixed=a.w, k_stride=100, max_batch=a.max_batch,
+                 slots=a.slots)
+    stats, _ = srv.run(arrivals, queries, ks, keep_results=False, realtime=True, log=log)
+    log(f"p50 {stats['p50_ms']:.2f} ms, p99 {stats['p99_ms']:.2f} ms, sustained "
+        f"{stats['sustained_qps']:.0f} q/s, mean batch {stats['mean_batch']:.0f}")
+
+    # recall on a sample, each request searched alone (same w, same k)
+    S = min(a.recall_sample, R)
+    sq, sk = queries[:S], ks[:S]
+    truth, _ = brute_force(gdb, torch.from_numpy(sq).to(dev), 10)
+    truth = truth.cpu().numpy().view(np.uint32)
+    rec = {}
+    for name, m in (("learned", model), ("fixed", None)):
+        s2 = Server(ix, model=m, w_fixed=a.w, k_stride=100, max_batch=1024, slots=1)
+        _, (ids, _) = s2.run(np.zeros(S), sq, sk, keep_results=True, realtime=False)
+        hits = [len(set(ids[i, :min(int(sk[i]), 10)].tolist()) &
+                    set(truth[i, :min(int(sk[i]), 10)].tolist())) / min(int(sk[i]), 10)
+                for i in range(S)]
+        rec[name] = float(np.mean(hits))
+    out = {"scenario": "serving loop", "n": a.n, "requests": R, "duration_s": a.duration,
+           "rate_qps": [a.lo, a.hi], "period_s": a.period, "k_mix": [1, 10, 100],
+           "w_fixed": a.w, "w_max": a.w_max, "delta": model.delta,
+           "recall_at_min_k_10": rec, "recall_sample": S, **stats}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
