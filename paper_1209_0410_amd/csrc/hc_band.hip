@@ -125,9 +125,12 @@ __global__ __launch_bounds__(256) void k_band_scatter(BandArgs a)
 // result gives lane l the sums of its query with 16 of every 32 rows (the
 // rows 8g + 4h + j, h = l / 32).  So every query has two lanes, each keeping a
 // list of the nearest entries among its half of the rows; the halves are
-// merged at the end.  A sum becomes a candidate only if it is at most the
-// current k-th distance of either half (ties are settled by the id inside);
-// only then are the window test, the id and the insertion paid for.
+// merged at the end.  The accumulator starts at floor(crow / 2), so the
+// product gives h = floor(crow / 2) + sum (127 - x)(q - 128) and the distance
+// is 2h + (crow mod 2) + cq: h <= floor((bound - cq) / 2) holds for every
+// distance within the bound, so h alone screens the pairs (four at a time).
+// Only a pair that passes pays for the exact distance, the window test, the id
+// and the insertion (ties are settled by the id there).
 // ---------------------------------------------------------------------------
 constexpr int kMW = 8;              // wavefronts per block
 constexpr int kMQ = 32;             // queries per wavefront
@@ -165,7 +168,8 @@ __global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(KR > 
 void k_band(BandArgs a)
 {
     __shared__ uint4 tile[kMRows * 8];
-    __shared__ __align__(16) int tile_c[kMRows];
+    __shared__ __align__(16) int tile_c[kMRows];     // floor(crow / 2)
+    __shared__ uint8_t tile_p[kMRows];               // crow mod 2
     __shared__ uint32_t tile_id[kMRows];
     __shared__ uint32_t wspan[2][kMW];
 
@@ -302,7 +306,9 @@ void k_band(BandArgs a)
             tile[mslot(lr, 2 * lf)] = xor4(x0, 0x7F7F7F7Fu);
             tile[mslot(lr, 2 * lf + 1)] = xor4(x1, 0x7F7F7F7Fu);
             if (lf == 0) {
-                tile_c[lr] = (int)(xx - 256u * sx);
+                const int crow = (int)(xx - 256u * sx);
+                tile_c[lr] = crow >> 1;
+                tile_p[lr] = (uint8_t)(crow & 1);
                 tile_id[lr] = xid;
             }
             __syncthreads();
@@ -327,13 +333,15 @@ void k_band(BandArgs a)
         const uint32_t rlo = lo > t0 ? std::min<uint32_t>(lo - t0, kMRows) : 0u;
         const uint32_t rhi = hi > t0 ? std::min<uint32_t>(hi - t0, kMRows) : 0u;
         if (!live || rlo >= rhi) th = INT32_MIN;
-        // A passing sum waits in a pending slot (its sum and tile row) and
-        // is inserted at the end of the tile, when the whole wavefront inserts
-        // at once; a lane inserts early only when a second sum passes.
-        int pend_t = 0;
+        int hb = th >> 1;       // screen: h <= floor(bound / 2)
+        // A passing pair waits in a pending slot (its h and tile row) and is
+        // inserted at the end of the tile, when the whole wavefront inserts at
+        // once; a lane inserts early only when a second pair passes.
+        int pend_h = 0;
         uint32_t pend_r = kNoRow;
         auto insert_pending = [&]() {
-            const uint64_t key = ((uint64_t)(uint32_t)(pend_t + cq) << 32) | tile_id[pend_r];
+            const int t = 2 * pend_h + (int)tile_p[pend_r];
+            const uint64_t key = ((uint64_t)(uint32_t)(t + cq) << 32) | tile_id[pend_r];
             if (key < L[KR - 1]) {
 #pragma unroll
                 for (int m = KR - 1; m > 0; m--)
@@ -341,12 +349,22 @@ void k_band(BandArgs a)
                 L[0] = key < L[0] ? key : L[0];
                 const int b = list_bound(L, cq);
                 th = b < th ? b : th;
+                hb = th >> 1;
             }
             pend_r = kNoRow;
         };
 #pragma unroll 1
         for (uint32_t rb = 0; rb < kMRows / 32; rb++) {
-            v16i acc = {};
+            // accumulator rows of this lane: 8g + 4h + j; start at floor(crow / 2)
+            v16i acc;
+#pragma unroll
+            for (int g = 0; g < 4; g++) {
+                const int4 cr = *reinterpret_cast<const int4 *>(&tile_c[rb * 32 + 8 * g + 4 * h]);
+                acc[4 * g] = cr.x;
+                acc[4 * g + 1] = cr.y;
+                acc[4 * g + 2] = cr.z;
+                acc[4 * g + 3] = cr.w;
+            }
             const uint32_t ar = rb * 32 + qn;
 #pragma unroll
             for (int s = 0; s < 4; s++) {
@@ -357,16 +375,14 @@ void k_band(BandArgs a)
 #pragma unroll
             for (int g = 0; g < 4; g++) {
                 const uint32_t r0 = rb * 32 + 8 * g + 4 * h;
-                const int4 cr = *reinterpret_cast<const int4 *>(&tile_c[r0]);
-                const int t[4] = {(acc[4 * g] << 1) + cr.x, (acc[4 * g + 1] << 1) + cr.y,
-                                  (acc[4 * g + 2] << 1) + cr.z, (acc[4 * g + 3] << 1) + cr.w};
-                const int tmin = std::min(std::min(t[0], t[1]), std::min(t[2], t[3]));
-                if (tmin <= th) {       // rare once the lists are full
+                const int hmin = std::min(std::min(acc[4 * g], acc[4 * g + 1]),
+                                          std::min(acc[4 * g + 2], acc[4 * g + 3]));
+                if (hmin <= hb) {       // rare once the lists are full
 #pragma unroll
                     for (int j = 0; j < 4; j++) {
-                        if (t[j] <= th && r0 + j - rlo < rhi - rlo) {
+                        if (acc[4 * g + j] <= hb && r0 + j - rlo < rhi - rlo) {
                             if (pend_r != kNoRow) insert_pending();
-                            pend_t = t[j];
+                            pend_h = acc[4 * g + j];
                             pend_r = r0 + j;
                         }
                     }
