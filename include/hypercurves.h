@@ -137,6 +137,38 @@ hc_status hc_insert_rows(const hc_index *idx, const uint8_t *d_db, uint64_t m, v
                          size_t index_bytes, void *d_scratch, size_t scratch_bytes,
                          hc_stream stream, hc_index **out);
 
+/* ---------------------------------------------------------------------- */
+/* Host-core search (the CPU side of the cooperative scheduler, Sec. 6)    */
+/* ---------------------------------------------------------------------- */
+
+/* The paper's scheduler (Alg. 3) answers a request on a CPU core when the
+ * ready requests are few enough for the cores, and batches it for the GPU
+ * otherwise.  These calls give the CPU side: host copies of the curve lists
+ * and Alg. 2 over them.  They never replace the GPU search: the caller chooses
+ * the host path per request.
+ *
+ * hc_host_index_bytes: bytes of the host copy (per curve n keys of 16 B, then
+ * per curve n ids).  hc_host_index_copy: copies the lists of idx into h_index
+ * (caller-owned host memory, at least those bytes) and waits for the copy;
+ * HC_ERR_SIZE if too small. */
+hc_status hc_host_index_bytes(const hc_index *idx, size_t *bytes);
+hc_status hc_host_index_copy(const hc_index *idx, void *h_index, size_t bytes,
+                             hc_stream stream);
+
+/* Alg. 2 on the calling thread for nq queries in host memory (nq x 128 uint8)
+ * against h_index (from hc_host_index_copy of idx) and h_db (the n x 128
+ * database in host memory): w = h_w[q] (or w_fixed), k = h_k[q] (or k_fixed;
+ * h_k entries are clamped to [1, k_stride]).  Row q of h_out_ids /
+ * h_out_dists (nq x k_stride) holds the k results, then 0xFFFFFFFF: the same
+ * rows hc_search_uneven writes, bit for bit.  Calls on distinct output
+ * buffers may run on concurrent threads.  Errors: null pointers, k_stride
+ * outside [1, HC_K_MAX], k_fixed outside [1, k_stride] (without h_k) ->
+ * HC_ERR_INVALID. */
+hc_status hc_host_search(const hc_index *idx, const void *h_index, const uint8_t *h_db,
+                         const uint8_t *h_queries, uint32_t nq, uint32_t w_fixed,
+                         const uint32_t *h_w, uint32_t k_fixed, const uint32_t *h_k,
+                         uint32_t k_stride, uint32_t *h_out_ids, uint32_t *h_out_dists);
+
 /* Frees the host handle only (the caller owns every device buffer). */
 hc_status hc_index_destroy(hc_index *idx);
 

@@ -1,5 +1,6 @@
-// Extended keys of a 16-dim point with 8-bit coordinates (gfx950): the
-// Hilbert key of the method and, for comparison, the Z-order key.
+// Extended keys of a 16-dim point with 8-bit coordinates: the Hilbert key of
+// the method and, for comparison, the Z-order key.  Compiled for gfx950 and
+// for the host search of the cooperative path.
 //
 // The curve is the Butz-type Hilbert curve the paper uses (Sec. 2.2.1), in the
 // transposed form of J. Skilling ("Programming the Hilbert curve", AIP Conf.
@@ -14,7 +15,7 @@ namespace hc {
 
 // 8x8 bit-matrix transpose of a 64-bit word whose byte r (r = 0 is the most
 // significant) is row r and whose bit 7-c is column c (Hacker's Delight 7-3).
-__device__ inline uint64_t transpose8x8(uint64_t x)
+__host__ __device__ inline uint64_t transpose8x8(uint64_t x)
 {
     uint64_t t;
     t = (x ^ (x >> 7)) & 0x00AA00AA00AA00AAull;
@@ -29,7 +30,7 @@ __device__ inline uint64_t transpose8x8(uint64_t x)
 // Moves the four bytes of a 32-bit word to the odd byte positions (counted
 // from the most significant byte) of a 64-bit word: b0 b1 b2 b3 ->
 // 0 b0 0 b1 0 b2 0 b3.
-__device__ inline uint64_t spread_bytes(uint32_t v)
+__host__ __device__ inline uint64_t spread_bytes(uint32_t v)
 {
     uint64_t x = v;
     x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
@@ -40,7 +41,7 @@ __device__ inline uint64_t spread_bytes(uint32_t v)
 // Bit-plane transpose of 16 8-bit values into a key: level 7 of dims 0..15,
 // then level 6, and so on.  Dims 0..7 and 8..15 are transposed as two 8x8 bit
 // matrices whose rows are interleaved byte by byte.
-__device__ inline Key interleave_key16(const uint32_t (&x)[kDpc])
+__host__ __device__ inline Key interleave_key16(const uint32_t (&x)[kDpc])
 {
     uint64_t a = 0, b = 0;
 #pragma unroll
@@ -56,7 +57,7 @@ __device__ inline Key interleave_key16(const uint32_t (&x)[kDpc])
     return k;
 }
 
-__device__ inline Key hilbert_key16(const uint32_t (&coord)[kDpc])
+__host__ __device__ inline Key hilbert_key16(const uint32_t (&coord)[kDpc])
 {
     uint32_t x[kDpc];
 #pragma unroll
@@ -94,18 +95,18 @@ __device__ inline Key hilbert_key16(const uint32_t (&coord)[kDpc])
 
 // Z-order (Morton) key: the coordinates' bits interleaved as they are, with
 // no Hilbert rotation.
-__device__ inline Key zorder_key16(const uint32_t (&coord)[kDpc])
+__host__ __device__ inline Key zorder_key16(const uint32_t (&coord)[kDpc])
 {
     return interleave_key16(coord);
 }
 
-__device__ inline Key curve_key16(const uint32_t (&coord)[kDpc], uint32_t curve)
+__host__ __device__ inline Key curve_key16(const uint32_t (&coord)[kDpc], uint32_t curve)
 {
     return curve == HC_CURVE_ZORDER ? zorder_key16(coord) : hilbert_key16(coord);
 }
 
 // Loads the 16 coordinates of curve c of a 128-byte row.
-__device__ inline void project16(const uint8_t *row, const IndexView &v, uint32_t c,
+__host__ __device__ inline void project16(const uint8_t *row, const IndexView &v, uint32_t c,
                                  uint32_t (&coord)[kDpc])
 {
     if (v.identity) {

@@ -104,7 +104,7 @@ hc_status band_search(const IndexView &v, const uint8_t *d_queries, uint32_t nq,
                       uint32_t *d_out_dists, void *d_scratch, size_t scratch_bytes,
                       hipStream_t st);
 
-__device__ inline bool key_less(const Key &a, const Key &b)
+__host__ __device__ inline bool key_less(const Key &a, const Key &b)
 {
     return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo);
 }

@@ -5,6 +5,7 @@ index build and of the search runs in libhypercurves.so.
 """
 import ctypes as ct
 
+import numpy as np
 import torch
 
 from . import capi
@@ -254,3 +255,43 @@ def brute_force(db, queries, k):
     capi.call("hc_brute_force", _ptr(db), db.shape[0], _ptr(queries), nq, k, _ptr(ids),
               _ptr(dists), _ptr(sc), sc.numel(), _stream())
     return ids, dists
+
+
+class HostSearch:
+    """Host copies of an index's curve lists and of its database: the CPU side
+    of the cooperative scheduler (the paper's Alg. 3).  search() runs Alg. 2 on
+    the calling thread through the same library (ctypes releases the GIL, so
+    calls on several threads run in parallel); its rows equal
+    Index.search_uneven's bit for bit."""
+
+    def __init__(self, ix, db_host):
+        self.ix = ix
+        sz = ct.c_size_t()
+        capi.call("hc_host_index_bytes", ix.handle, ct.byref(sz))
+        self.lists = np.empty(sz.value, np.uint8)
+        capi.call("hc_host_index_copy", ix.handle, self.lists.ctypes.data_as(ct.c_void_p),
+                  sz.value, _stream())
+        self.db = np.ascontiguousarray(db_host, dtype=np.uint8)
+        if self.db.shape != (ix.n, 128):
+            raise ValueError("db_host must be the index's (n, 128) uint8 database")
+
+    def search(self, queries, w=16, k=10, k_stride=None, w_per_query=None, k_per_query=None,
+               out=None):
+        """(ids, dists) uint32 arrays (nq, k_stride) for host queries (nq, 128)."""
+        q = np.ascontiguousarray(queries, dtype=np.uint8)
+        nq = q.shape[0]
+        if k_stride is None:
+            k_stride = int(np.max(k_per_query)) if k_per_query is not None else int(k)
+        if out is None:
+            out = (np.empty((nq, k_stride), np.uint32), np.empty((nq, k_stride), np.uint32))
+
+        def p(a):
+            return None if a is None else np.ascontiguousarray(a, np.uint32).ctypes.data_as(
+                ct.c_void_p)
+        wp = None if w_per_query is None else np.ascontiguousarray(w_per_query, np.uint32)
+        kp = None if k_per_query is None else np.ascontiguousarray(k_per_query, np.uint32)
+        capi.call("hc_host_search", self.ix.handle, self.lists.ctypes.data_as(ct.c_void_p),
+                  self.db.ctypes.data_as(ct.c_void_p), q.ctypes.data_as(ct.c_void_p), nq,
+                  int(w), p(wp), int(k), p(kp), k_stride,
+                  out[0].ctypes.data_as(ct.c_void_p), out[1].ctypes.data_as(ct.c_void_p))
+        return out

@@ -8,6 +8,14 @@ overlap on the device while new requests keep arriving.  This is the online
 setting of the paper's Sec. 6 (tasks arrive continuously; the group size is
 decided at run time), with slots on streams in place of its CPU/GPU buffers.
 
+With host cores given (a HostSearch and cpu_workers), the loop is the
+paper's cooperative scheduler (Sec. 6, Alg. 3): while the requests waiting
+are no more than the host workers, each goes to a host core, where one
+request costs no device launch; when more are waiting, they are batched for
+the GPU as a stream slot frees up, and idle host workers take requests from
+the front meanwhile.  Host and GPU give the same rows for a request (same w,
+same k), so results do not depend on where a request ran.
+
 The arrival process is seeded: Poisson with a rate that varies sinusoidally,
 drawn by thinning (Lewis & Shedler).
 """
@@ -17,6 +25,7 @@ import json
 import math
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import torch
@@ -84,12 +93,18 @@ def batch_bytes(nq, k_stride, curves=8, max_split=32):
 
 
 class Server:
-    """Admits arriving requests into batches on `slots` streams."""
+    """Admits arriving requests into batches on `slots` streams; with `host`
+    (an index.HostSearch) and cpu_workers > 0, short queues go to host cores
+    (fixed w only: the learned w is inferred on the GPU)."""
 
     def __init__(self, ix, model=None, w_fixed=64, k_stride=100, max_batch=4096, slots=3,
-                 budget=None, cfg=None, w_fallback=None):
+                 budget=None, cfg=None, w_fallback=None, host=None, cpu_workers=0):
+        if host is not None and model is not None:
+            raise ValueError("the host path takes the fixed w; use model=None with host")
         self.ix = ix
         self.model = model
+        self.host = host
+        self.cpu_workers = int(cpu_workers) if host is not None else 0
         self.w_fixed = int(w_fixed)
         self.w_fallback = int(w_fallback if w_fallback is not None else w_fixed)
         self.k_stride = int(k_stride)
@@ -136,15 +151,38 @@ class Server:
         res_ids = np.zeros((R, self.k_stride), np.uint32) if keep_results else None
         res_d = np.zeros((R, self.k_stride), np.uint32) if keep_results else None
         inflight = collections.deque()      # (slot, lo, hi, bytes)
+        cpu_inflight = []                    # futures of host-core requests
+        pool = ThreadPoolExecutor(self.cpu_workers) if self.cpu_workers else None
         nxt = 0
         batches = 0
+        on_cpu = 0
         sizes = []
         t0 = time.perf_counter()
         clock = (lambda: time.perf_counter() - t0) if realtime else None
         arrivals = np.asarray(arrivals, np.float64)
         next_log = 5.0
-        while nxt < R or inflight:
+        qa = np.ascontiguousarray(queries, np.uint8)
+        ka = np.ascontiguousarray(ks, np.uint32)
+
+        def on_host(i):
+            ids, d = self.host.search(qa[i:i + 1], w=self.w_fixed, k_stride=self.k_stride,
+                                      k_per_query=ka[i:i + 1])
+            return i, time.perf_counter() - t0, ids[0], d[0]
+
+        while nxt < R or inflight or cpu_inflight:
             now = clock() if realtime else math.inf
+            # retire finished host-core requests
+            if cpu_inflight:
+                still = []
+                for f in cpu_inflight:
+                    if f.done():
+                        i, t_done, ids, d = f.result()
+                        done_at[i] = t_done if realtime else 0.0
+                        if keep_results:
+                            res_ids[i], res_d[i] = ids, d
+                    else:
+                        still.append(f)
+                cpu_inflight = still
             # retire finished batches (oldest first; each slot records one event)
             for _ in range(len(inflight)):
                 slot, lo, hi, nb = inflight[0]
@@ -164,8 +202,18 @@ class Server:
                 next_log += 5.0
             # admit what has arrived into a free slot, as much as the budget allows
             arrived = R if not realtime else int(np.searchsorted(arrivals, now, side="right"))
-            ready_end = min(arrived, nxt + self.max_batch)
             free = [s for s in self.slots if not s.busy]
+            if pool is not None and arrived > nxt:
+                idle_cpu = self.cpu_workers - len(cpu_inflight)
+                ready = arrived - nxt
+                # few waiting: the host cores take them; many waiting and the
+                # GPU busy: idle host cores take some from the front
+                take = min(ready, idle_cpu) if (ready <= self.cpu_workers or not free) else 0
+                for i in range(nxt, nxt + take):
+                    cpu_inflight.append(pool.submit(on_host, i))
+                nxt += take
+                on_cpu += take
+            ready_end = min(arrived, nxt + self.max_batch)
             if ready_end > nxt and free:
                 per = batch_bytes(1, self.k_stride)
                 fit = (self.budget.budget - self.budget.used) // per
@@ -183,11 +231,15 @@ class Server:
                 self.budget.refused += 1
             if not realtime and not free and inflight:
                 inflight[0][0].done.synchronize()
-            elif realtime and nxt < R and ready_end == nxt and not inflight:
+            elif realtime and nxt < R and ready_end == nxt and not inflight and not cpu_inflight:
                 time.sleep(max(0.0, min(arrivals[nxt] - now, 0.001)))
+            elif cpu_inflight and ready_end == nxt:
+                time.sleep(2e-5)            # let the host workers run
         torch.cuda.synchronize()
+        if pool is not None:
+            pool.shutdown()
         lat = done_at - np.asarray(arrivals) if realtime else None
-        stats = {"requests": R, "batches": batches,
+        stats = {"requests": R, "batches": batches, "on_host_cores": on_cpu,
                  "mean_batch": float(np.mean(sizes)) if sizes else 0.0,
                  "max_batch": int(max(sizes)) if sizes else 0,
                  "hbm_budget": self.budget.budget, "hbm_peak": self.budget.peak,
@@ -310,5 +362,54 @@ def main(argv=None):
     print(json.dumps(out), flush=True)
 
 
+def cooperative_main(argv=None):
+    """The cooperative scheduler against the GPU alone: constant Poisson rates
+    over a resident index, fixed w, k from {1, 10, 100}; p50/p99 per rate with
+    and without host cores.  Prints one JSON line."""
+    from . import datagen
+    from .index import HostSearch, Index
+    ap = argparse.ArgumentParser(prog="python -m paper_1209_0410_amd.serve --cooperative")
+    ap.add_argument("--cooperative", action="store_true")
+    ap.add_argument("--n", type=int, default=10_000_000)
+    ap.add_argument("--w", type=int, default=16)
+    ap.add_argument("--rates", default="1000,5000,20000,100000")
+    ap.add_argument("--duration", type=float, default=10.0)
+    ap.add_argument("--cpu-workers", type=int, default=12)
+    ap.add_argument("--slots", type=int, default=3)
+    a = ap.parse_args(argv)
+
+    def log(msg):
+        print(f"[serve] {msg}", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    db = datagen.make_db(a.n)
+    ix = Index(torch.from_numpy(db).to(dev))
+    host = HostSearch(ix, db)
+    log(f"{a.n} rows resident on the GPU and in host memory")
+    rows = []
+    for rate in [float(x) for x in a.rates.split(",")]:
+        arr = sinusoidal_arrivals(a.duration, rate, rate, a.duration, seed=datagen.SEED_ARRIVALS)
+        R = len(arr)
+        q = datagen.make_queries(R, seed=datagen.SEED_EVAL)
+        ks = np.random.default_rng(datagen.SEED_ARRIVALS).choice(
+            np.array([1, 10, 100], np.uint32), size=R)
+        row = {"rate_qps": rate, "requests": R}
+        for name, cw in (("gpu", 0), ("cooperative", a.cpu_workers)):
+            srv = Server(ix, w_fixed=a.w, k_stride=100, max_batch=16_384, slots=a.slots,
+                         host=host if cw else None, cpu_workers=cw)
+            st, _ = srv.run(arr, q, ks, keep_results=False, realtime=True)
+            row[name] = {k: st[k] for k in ("p50_ms", "p99_ms", "mean_ms", "sustained_qps",
+                                            "batches", "mean_batch", "on_host_cores")}
+            log(f"rate {rate:.0f}/s {name}: p50 {st['p50_ms']:.3f} ms, p99 "
+                f"{st['p99_ms']:.3f} ms, {st['on_host_cores']} of {R} on host cores")
+        rows.append(row)
+    print(json.dumps({"scenario": "cooperative scheduler", "n": a.n, "w": a.w,
+                      "cpu_workers": a.cpu_workers, "duration_s": a.duration,
+                      "k_mix": [1, 10, 100], "rates": rows}), flush=True)
+
+
 if __name__ == "__main__":
-    main()
+    if "--cooperative" in sys.argv[1:]:
+        cooperative_main()
+    else:
+        main()

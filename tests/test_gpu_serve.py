@@ -102,3 +102,41 @@ def test_learned_w_per_request_in_the_mix(env):
     sel = np.arange(0, R, 9)
     ai, ad = alone(env["gix"], env["q"][sel], env["ks"][sel], w[sel])
     assert (ids[sel] == ai).all() and (d[sel] == ad).all()
+
+
+def test_host_search_equals_gpu(env):
+    """The host-core search (the CPU side of the cooperative scheduler) gives the
+    GPU's rows bit for bit, from a host copy of the device lists."""
+    import torch
+    from paper_1209_0410_amd.index import HostSearch
+    host = HostSearch(env["gix"], env["db"])
+    rng = np.random.default_rng(31)
+    R = 600
+    q = env["q"][:R]
+    w = rng.integers(0, 200, size=R).astype(np.uint32)
+    w[:2] = [0, 60_000]
+    ks = env["ks"][:R]
+    gi, gd = env["gix"].search_uneven(
+        torch.from_numpy(q).cuda(), w_per_query=torch.from_numpy(w.view(np.int32)).cuda(),
+        k_per_query=torch.from_numpy(ks.view(np.int32)).cuda(), k_stride=100)
+    hi_, hd = host.search(q, k_stride=100, w_per_query=w, k_per_query=ks)
+    assert (u32(gi) == hi_).all() and (u32(gd) == hd).all()
+
+
+def test_cooperative_scheduler_same_results(env):
+    """A short queue goes to host cores, a burst to the GPU (and to idle host
+    cores from the front); every request's row equals its GPU row alone."""
+    from paper_1209_0410_amd.index import HostSearch
+    from paper_1209_0410_amd.serve import Server
+    host = HostSearch(env["gix"], env["db"])
+    R = 2400
+    arr = np.concatenate([np.arange(400) * 1e-3, np.full(R - 400, 0.45)])
+    srv = Server(env["gix"], w_fixed=24, k_stride=100, max_batch=512, slots=2, host=host,
+                 cpu_workers=4)
+    stats, (ids, d) = srv.run(arr, env["q"][:R], env["ks"][:R])
+    assert stats["requests"] == R
+    assert stats["on_host_cores"] > 0 and stats["batches"] > 0
+    w = np.full(R, 24)
+    sel = np.arange(0, R, 5)
+    ai, ad = alone(env["gix"], env["q"][sel], env["ks"][sel], w[sel])
+    assert (ids[sel] == ai).all() and (d[sel] == ad).all()
