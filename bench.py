@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--w-max", type=int, default=1 << 17)
     ap.add_argument("--latency-batch", type=int, default=1000)
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--rowstore", type=int, default=1,
+                    help="attach the row store (curve-ordered rows) for the banded path")
     ap.add_argument("--f4", type=int, default=1,
                     help="Z-order comparison and incremental insertion (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -95,6 +97,13 @@ def main():
     build_s = time.time() - t0
     rank = learned.ranks(ix)
     log(f"index build {build_s:.3f}s ({ix.index_bytes / 1e9:.2f} GB)")
+    rowstore_bytes, rowstore_s = 0, 0.0
+    if a.rowstore:
+        t0 = time.time()
+        rowstore_bytes = ix.attach_rowstore()
+        torch.cuda.synchronize()
+        rowstore_s = time.time() - t0
+        log(f"row store {rowstore_bytes / 1e9:.2f} GB in {rowstore_s:.3f}s")
 
     stream = torch.cuda.current_stream()
     sc = ix.scratch(a.nq)
@@ -247,7 +256,8 @@ def main():
                                f"{'learned' if use_learned else 'fixed'} w calibrated to "
                                f"recall@10>=0.90",
                    "n": a.n, "nq": a.nq, "k": k, "curves": 8,
-                   "method": "learned-w" if use_learned else "fixed-w"},
+                   "method": "learned-w" if use_learned else "fixed-w",
+                   "rowstore_bytes": rowstore_bytes},
         "recall_at_10": head["recall"],
         "recall_target_met": bool(head["recall"] >= TARGET),
         "recall_queries": rq,
@@ -257,6 +267,7 @@ def main():
         "latency_ms": {"batch": lb, "p50": float(np.percentile(lat_ms, 50)),
                        "p99": float(np.percentile(lat_ms, 99))},
         "build_s": build_s,
+        "rowstore_s": rowstore_s,
         "sweep": rows,
         "uneven": uneven,
         "f4": f4,

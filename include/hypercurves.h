@@ -241,6 +241,24 @@ hc_status hc_search_encoded_ex(const hc_index *idx, const uint8_t *d_queries, ui
                                uint32_t *d_out_ids, uint32_t *d_out_dists, void *d_scratch,
                                size_t scratch_bytes, uint32_t path, hc_stream stream);
 
+/* Row store: for the banded path, each curve's rows copied in list order
+ * (stored as 127 - x, the form the matrix products take) with their crow =
+ * sum x (x - 256).  The banded search then streams contiguous memory instead
+ * of gathering rows by id.  It trades memory for locality: curves * n * 132 B
+ * (10.6 GB at n = 10^7).  Results are unchanged.
+ *
+ * hc_rowstore_bytes: bytes of the store.  hc_rowstore_build: fills d_rows
+ * (caller-owned device memory, 256-byte aligned, at least those bytes) from
+ * the index and its database on `stream`, and attaches it to idx: searches
+ * enqueued after it on the same stream use it (on other streams, after the
+ * stream has been synchronised).  The caller keeps d_rows alive while
+ * attached.  hc_rowstore_detach: the banded path gathers rows by id again.
+ * An index made by hc_insert_rows starts without a store.  Errors: null or
+ * misaligned pointers -> HC_ERR_INVALID; too small -> HC_ERR_SIZE. */
+hc_status hc_rowstore_bytes(const hc_index *idx, size_t *bytes);
+hc_status hc_rowstore_build(hc_index *idx, void *d_rows, size_t bytes, hc_stream stream);
+hc_status hc_rowstore_detach(hc_index *idx);
+
 /* Uneven batches: every query has its own w and its own k.  A query's window
  * slots (up to 16 w) are cut into work items of at most chunk_slots slots
  * (at most max_split items per query; the chunk grows beyond that); a

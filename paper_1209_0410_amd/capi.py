@@ -45,6 +45,9 @@ SIGNATURES = {
     "hc_index_attach": [_pp, _vp, _u64, _vp, _sz, ct.POINTER(_vp)],
     "hc_insert_bytes": [_vp, _u64, ct.POINTER(_sz), ct.POINTER(_sz)],
     "hc_host_index_bytes": [_vp, ct.POINTER(_sz)],
+    "hc_rowstore_bytes": [_vp, ct.POINTER(_sz)],
+    "hc_rowstore_build": [_vp, _vp, _sz, _vp],
+    "hc_rowstore_detach": [_vp],
     "hc_host_index_copy": [_vp, _vp, _sz, _vp],
     "hc_host_search": [_vp, _vp, _vp, _vp, _u32, _u32, _vp, _u32, _vp, _u32, _vp, _vp],
     "hc_insert_rows": [_vp, _vp, _u64, _vp, _sz, _vp, _sz, _vp, ct.POINTER(_vp)],

@@ -163,7 +163,7 @@ __device__ inline int list_bound(const uint64_t (&L)[KR], int cq)
 // bound is safe: a curve's list holds k distinct candidates of the union, so
 // the final k-th distance is at most its k-th distance, and a sum above the
 // bound cannot reach the result.  The results do not depend on the timing.
-template <int KR>
+template <int KR, bool ROWS>
 __global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(KR > 10 ? 3 : 4)))
 void k_band(BandArgs a)
 {
@@ -266,31 +266,60 @@ void k_band(BandArgs a)
         return U0 + j * kMRows;
     };
 
-    // loader: thread t fills 32 bytes (parts 2f, 2f + 1) of tile row t / 4;
-    // the ids run two tiles ahead of the rows, the rows one tile ahead of the
-    // matrix work
+    // loader: thread t fills 32 bytes (parts 2f, 2f + 1) of tile row t / 4.
+    // From the database, the ids run two tiles ahead of the rows, the rows one
+    // tile ahead of the matrix work; from the row store (the rows of this
+    // curve in list order, already 127 - x, and their crow) rows, crow and ids
+    // all come one tile ahead.  Rows past the union (the last tile's tail)
+    // read a valid row: they lie outside every window and are never offered.
     const uint32_t *ids = a.v.ids[c];
     const uint32_t lr = (uint32_t)tid >> 2, lf = (uint32_t)tid & 3;
     auto load_id = [&](uint32_t i) -> uint32_t {
         const uint64_t e = (uint64_t)tile_start(i) + lr;
         return e < U1 ? ids[e] : kEmpty;
     };
-    // rows past the union (the last tile's tail) read row 0: they lie outside
-    // every window and are never offered
     uint4 x0 = make_uint4(0, 0, 0, 0), x1 = x0;
+    int xcrow = 0;
     auto load_row = [&](uint32_t id) {
         const uint64_t r = id != kEmpty ? id : 0u;
         const uint4 *src = reinterpret_cast<const uint4 *>(a.v.db + r * kDim) + 2 * lf;
         x0 = src[0];
         x1 = src[1];
     };
-    uint32_t xid = T > 0 ? load_id(0) : kEmpty;
-    uint32_t id_next = T > 1 ? load_id(1) : kEmpty;
-    if (T > 0) load_row(xid);
+    uint32_t xid = kEmpty, id_next = kEmpty;
+    auto load_stored = [&](uint32_t i) {
+        const uint64_t e = (uint64_t)tile_start(i) + lr;
+        const uint64_t r = e < U1 ? e : 0u;
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.v.rows[c] + r * kDim) + 2 * lf;
+        x0 = src[0];
+        x1 = src[1];
+        if (lf == 0) {
+            xcrow = a.v.crow[c][r];
+            xid = e < U1 ? ids[e] : kEmpty;
+        }
+    };
+    if constexpr (ROWS) {
+        if (T > 0) load_stored(0);
+    } else {
+        xid = T > 0 ? load_id(0) : kEmpty;
+        id_next = T > 1 ? load_id(1) : kEmpty;
+        if (T > 0) load_row(xid);
+    }
 
     for (uint32_t i = 0; i < T; i++) {
         const uint32_t t0 = tile_start(i);
-        {   // publish the fetched rows
+        if constexpr (ROWS) {   // publish the fetched rows
+            __syncthreads();
+            tile[mslot(lr, 2 * lf)] = x0;
+            tile[mslot(lr, 2 * lf + 1)] = x1;
+            if (lf == 0) {
+                tile_c[lr] = xcrow >> 1;
+                tile_p[lr] = (uint8_t)(xcrow & 1);
+                tile_id[lr] = xid;
+            }
+            __syncthreads();
+            if (i + 1 < T) load_stored(i + 1);
+        } else {
             uint32_t xx = 0, sx = 0;
             const uint32_t parts[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
 #pragma unroll
@@ -312,12 +341,12 @@ void k_band(BandArgs a)
                 tile_id[lr] = xid;
             }
             __syncthreads();
+            if (i + 1 < T) {
+                xid = id_next;
+                load_row(xid);
+            }
+            if (i + 2 < T) id_next = load_id(i + 2);
         }
-        if (i + 1 < T) {
-            xid = id_next;
-            load_row(xid);
-        }
-        if (i + 2 < T) id_next = load_id(i + 2);
         if ((i & 7) == 7) read_bound();
         if (!(t0 < u1 && (uint64_t)t0 + kMRows > u0)) continue;       // wavefront-uniform
 
@@ -366,11 +395,25 @@ void k_band(BandArgs a)
                 acc[4 * g + 3] = cr.w;
             }
             const uint32_t ar = rb * 32 + qn;
+            if constexpr (KR <= 10) {
+                // the four A operands are read before the chain, so that their
+                // LDS latencies overlap (the longest list has no registers for it)
+                uint4 av[4];
 #pragma unroll
-            for (int s = 0; s < 4; s++) {
-                const uint4 av = tile[mslot(ar, 2 * s + h)];
-                acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                    v4i{(int)av.x, (int)av.y, (int)av.z, (int)av.w}, bq[s], acc, 0, 0, 0);
+                for (int s = 0; s < 4; s++) av[s] = tile[mslot(ar, 2 * s + h)];
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int s = 0; s < 4; s++)
+                    acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                        v4i{(int)av[s].x, (int)av[s].y, (int)av[s].z, (int)av[s].w}, bq[s],
+                        acc, 0, 0, 0);
+            } else {
+#pragma unroll
+                for (int s = 0; s < 4; s++) {
+                    const uint4 av = tile[mslot(ar, 2 * s + h)];
+                    acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                        v4i{(int)av.x, (int)av.y, (int)av.z, (int)av.w}, bq[s], acc, 0, 0, 0);
+                }
             }
 #pragma unroll
             for (int g = 0; g < 4; g++) {
@@ -436,6 +479,55 @@ __global__ __launch_bounds__(64) void k_band_merge(BandArgs a)
     });
 }
 
+// Row store of curve c: 8 lanes per list entry, each 16 bytes of the row
+// (127 - x) and its part of crow, reduced over the 8 lanes.
+__global__ __launch_bounds__(256) void k_rowstore(IndexView v, uint32_t c, uint8_t *rows,
+                                                  int *crow)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t e = t >> 3;
+    const uint32_t part = (uint32_t)t & 7;
+    const bool valid = e < v.n;
+    const uint32_t id = valid ? v.ids[c][e] : 0u;
+    const uint4 x = valid ? reinterpret_cast<const uint4 *>(v.db + (uint64_t)id * kDim)[part]
+                          : make_uint4(0, 0, 0, 0);
+    uint32_t xx = __builtin_amdgcn_udot4(x.x, x.x, 0u, false);
+    xx = __builtin_amdgcn_udot4(x.y, x.y, xx, false);
+    xx = __builtin_amdgcn_udot4(x.z, x.z, xx, false);
+    xx = __builtin_amdgcn_udot4(x.w, x.w, xx, false);
+    uint32_t sx = __builtin_amdgcn_udot4(x.x, 0x01010101u, 0u, false);
+    sx = __builtin_amdgcn_udot4(x.y, 0x01010101u, sx, false);
+    sx = __builtin_amdgcn_udot4(x.z, 0x01010101u, sx, false);
+    sx = __builtin_amdgcn_udot4(x.w, 0x01010101u, sx, false);
+#pragma unroll
+    for (int m = 1; m < 8; m <<= 1) {
+        xx += __shfl_xor(xx, m, 64);
+        sx += __shfl_xor(sx, m, 64);
+    }
+    if (valid) {
+        reinterpret_cast<uint4 *>(rows + e * kDim)[part] = xor4(x, 0x7F7F7F7Fu);
+        if (part == 0) crow[e] = (int)(xx - 256u * sx);
+    }
+}
+
+struct RowStoreLayout {
+    size_t rows_off[kMaxCurves], crow_off[kMaxCurves], total;
+};
+
+static RowStoreLayout rowstore_layout(uint32_t curves, uint64_t n)
+{
+    RowStoreLayout L{};
+    size_t off = 0;
+    for (uint32_t c = 0; c < curves; c++) {
+        L.rows_off[c] = off;
+        off = align256(off + (size_t)kDim * n);
+        L.crow_off[c] = off;
+        off = align256(off + sizeof(int) * n);
+    }
+    L.total = off;
+    return L;
+}
+
 size_t band_scratch_bytes(uint32_t curves, uint64_t n, uint32_t nq)
 {
     return band_layout(curves, n, nq).total;
@@ -479,12 +571,63 @@ hc_status band_search(const IndexView &v, const uint8_t *d_queries, uint32_t nq,
     hipLaunchKernelGGL(k_band_scatter, dim3((uint32_t)((nt + 255) / 256)), dim3(256), 0, st, a);
     const uint32_t blocks = (uint32_t)(((uint64_t)nq + kMBlockQ - 1) / kMBlockQ) * v.curves;
     const dim3 grid(blocks), block(kMThreads);
-    if (k == 1) hipLaunchKernelGGL(k_band<1>, grid, block, 0, st, a);
-    else if (k <= 4) hipLaunchKernelGGL(k_band<4>, grid, block, 0, st, a);
-    else if (k <= 10) hipLaunchKernelGGL(k_band<10>, grid, block, 0, st, a);
-    else hipLaunchKernelGGL(k_band<kBandK>, grid, block, 0, st, a);
+    if (v.rows[0]) {
+        if (k == 1) hipLaunchKernelGGL((k_band<1, true>), grid, block, 0, st, a);
+        else if (k <= 4) hipLaunchKernelGGL((k_band<4, true>), grid, block, 0, st, a);
+        else if (k <= 10) hipLaunchKernelGGL((k_band<10, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_band<kBandK, true>), grid, block, 0, st, a);
+    } else {
+        if (k == 1) hipLaunchKernelGGL((k_band<1, false>), grid, block, 0, st, a);
+        else if (k <= 4) hipLaunchKernelGGL((k_band<4, false>), grid, block, 0, st, a);
+        else if (k <= 10) hipLaunchKernelGGL((k_band<10, false>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_band<kBandK, false>), grid, block, 0, st, a);
+    }
     hipLaunchKernelGGL(k_band_merge, dim3(nq), dim3(64), 0, st, a);
     return last_hip();
 }
 
 }  // namespace hc
+
+using namespace hc;
+
+extern "C" {
+
+hc_status hc_rowstore_bytes(const hc_index *idx, size_t *bytes)
+{
+    if (!idx || !bytes) return HC_ERR_INVALID;
+    *bytes = rowstore_layout(idx->v.curves, idx->v.n).total;
+    return HC_OK;
+}
+
+hc_status hc_rowstore_build(hc_index *idx, void *d_rows, size_t bytes, hc_stream stream)
+{
+    if (!idx || !d_rows || ((uintptr_t)d_rows & 255)) return HC_ERR_INVALID;
+    const RowStoreLayout L = rowstore_layout(idx->v.curves, idx->v.n);
+    if (bytes < L.total) return HC_ERR_SIZE;
+    const uint64_t threads = idx->v.n * 8;
+    uint8_t *base = (uint8_t *)d_rows;
+    for (uint32_t c = 0; c < idx->v.curves; c++) {
+        hipLaunchKernelGGL(k_rowstore, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0,
+                           (hipStream_t)stream, idx->v, c, base + L.rows_off[c],
+                           (int *)(base + L.crow_off[c]));
+    }
+    const hc_status st = last_hip();
+    if (st != HC_OK) return st;
+    for (uint32_t c = 0; c < idx->v.curves; c++) {
+        idx->v.rows[c] = base + L.rows_off[c];
+        idx->v.crow[c] = (const int *)(base + L.crow_off[c]);
+    }
+    return HC_OK;
+}
+
+hc_status hc_rowstore_detach(hc_index *idx)
+{
+    if (!idx) return HC_ERR_INVALID;
+    for (uint32_t c = 0; c < kMaxCurves; c++) {
+        idx->v.rows[c] = nullptr;
+        idx->v.crow[c] = nullptr;
+    }
+    return HC_OK;
+}
+
+}  // extern "C"

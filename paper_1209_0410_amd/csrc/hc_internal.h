@@ -32,6 +32,10 @@ struct IndexView {
     uint16_t perm[kMaxCurves * kDpc];
     uint32_t identity;                        // perm is 16c + j
     uint32_t curve;                           // HC_CURVE_HILBERT or HC_CURVE_ZORDER
+    // optional row store: curve c's rows in list order, stored as 127 - x,
+    // and crow = sum x (x - 256) of each (null when absent)
+    const uint8_t *rows[kMaxCurves];
+    const int *crow[kMaxCurves];
 };
 
 }  // namespace hc

@@ -87,6 +87,19 @@ class Index:
         self._scratch = None
         return self
 
+    def attach_rowstore(self):
+        """Builds and attaches the row store (the rows of every curve in list
+        order, for the banded path); returns its size in bytes."""
+        sz = ct.c_size_t()
+        capi.call("hc_rowstore_bytes", self.handle, ct.byref(sz))
+        self.rowstore = _empty_bytes(sz.value, self.db.device)
+        capi.call("hc_rowstore_build", self.handle, _ptr(self.rowstore), sz.value, _stream())
+        return sz.value
+
+    def detach_rowstore(self):
+        capi.call("hc_rowstore_detach", self.handle)
+        self.rowstore = None
+
     def insert(self, db):
         """Index over `db`, whose first n rows are this index's rows, made by
         inserting rows n .. (no rebuild); equal to Index(db) bit for bit.  This

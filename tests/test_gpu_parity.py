@@ -190,3 +190,38 @@ def test_auto_path_matches_both(c1):
         b = c1["gix"].search(c1["gq"], 10, w, path=2)
         for x, y in ((a, g), (g, b)):
             assert (u32(x[0]) == u32(y[0])).all() and (u32(x[1]) == u32(y[1])).all()
+
+
+@pytest.mark.parametrize("k,w", [(10, 64), (1, 16), (16, 256), (4, 3000), (10, 0), (7, 20_000)])
+def test_rowstore_banded_bit_exact(c1, k, w):
+    """With the row store attached (rows in list order, read contiguously), the
+    banded search gives the same results."""
+    gix = c1["gix"]
+    gix.attach_rowstore()
+    try:
+        ids, d = gix.search(c1["gq"], k, w, path=2)
+    finally:
+        gix.detach_rowstore()
+    rid, rd = c1["oix"].search(c1["q"], k, w)
+    assert (u32(ids) == rid).all() and (u32(d) == rd).all()
+
+
+@pytest.mark.parametrize("n", [1, 65, 4097])
+def test_rowstore_small_shapes_and_per_query_w(oracle, torch_mod, n):
+    from paper_1209_0410_amd import datagen
+    from paper_1209_0410_amd.index import Index
+    db = datagen.make_rows(n, 41)
+    if n > 100:
+        db[50::50] = db[3]
+    q = datagen.make_rows(300, 42)
+    q[0] = db[0]
+    print(f"[rowstore] n={n}", flush=True)
+    gix = Index(torch_mod.from_numpy(db).cuda())
+    gix.attach_rowstore()
+    oix = oracle.Index(db)
+    gq = torch_mod.from_numpy(q).cuda()
+    w = np.random.default_rng(43).integers(0, 2 * n + 2, size=300).astype(np.uint32)
+    gw = torch_mod.from_numpy(w.view(np.int32)).cuda()
+    ids, d = gix.search(gq, 10, int(w.max()), w_per_query=gw, path=2)
+    rid, rd = oix.search(q, 10, w)
+    assert (u32(ids) == rid).all() and (u32(d) == rd).all()
