@@ -222,13 +222,13 @@ hc_status hc_search_encoded(const hc_index *idx, const uint8_t *d_queries, uint3
 /* Execution paths of the search; both give identical results.
  *  HC_PATH_GATHER: one wavefront per query gathers its candidates' rows.
  *  HC_PATH_BAND:   per curve, the batch ordered by place in the list; one
- *                  block per 256 neighbouring queries streams the union of
+ *                  block per 128 or 256 neighbouring queries streams the union of
  *                  their windows once, the distances of every query to every
  *                  streamed row come from the int8 matrix cores, and each
  *                  query keeps the entries inside its own window (for large
  *                  batches with large windows, where one list entry lies in
  *                  many windows).  k <= 16.
- *  HC_PATH_AUTO:   banded when 2 w nq >= 6 n (w = w_fixed or the hint), k <= 16
+ *  HC_PATH_AUTO:   banded when 2 w nq >= 3.5 n (w = w_fixed or the hint), k <= 16
  *                  and the scratch holds hc_search_scratch_bytes; else gather.
  * hc_search_encoded is hc_search_encoded_ex with HC_PATH_AUTO. */
 #define HC_PATH_AUTO 0u

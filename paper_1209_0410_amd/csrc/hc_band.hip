@@ -117,8 +117,8 @@ __global__ __launch_bounds__(256) void k_band_scatter(BandArgs a)
 // one chain of four v_mfma_i32_32x32x32_i8 (K = 128).  Every term is an
 // exact integer: the distance is the same uint32 as the byte-wise one.
 //
-// Block: kMW wavefronts, 32 queries each, consecutive in curve c's order.  The
-// block streams the union of its queries' windows through LDS, kMRows entries
+// Block: NW wavefronts, 32 queries each, consecutive in curve c's order.  The
+// block streams the union of its queries' windows through LDS, 16 NW entries
 // per tile (rows stored as 127 - x, 16-byte parts XOR-swizzled against bank
 // conflicts; crow and the id of each row beside them).  Lane l of a wavefront
 // holds query l % 32 as the B operand; the tile's rows are the A operand; the
@@ -132,11 +132,11 @@ __global__ __launch_bounds__(256) void k_band_scatter(BandArgs a)
 // Only a pair that passes pays for the exact distance, the window test, the id
 // and the insertion (ties are settled by the id there).
 // ---------------------------------------------------------------------------
-constexpr int kMW = 8;              // wavefronts per block
 constexpr int kMQ = 32;             // queries per wavefront
-constexpr int kMRows = 128;         // list entries per LDS tile
-constexpr int kMThreads = 64 * kMW;
-constexpr int kMBlockQ = kMW * kMQ;
+// Wavefronts per block: 8 shares each streamed row among 256 queries (large
+// windows, where the rows dominate); 4 keeps blocks small and many (windows
+// below kBandWideW, where a block's union is mostly the span of its places).
+constexpr uint32_t kBandWideW = 8192;
 constexpr uint32_t kNoRow = 0xFFFFFFFFu;
 
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -163,10 +163,14 @@ __device__ inline int list_bound(const uint64_t (&L)[KR], int cq)
 // bound is safe: a curve's list holds k distinct candidates of the union, so
 // the final k-th distance is at most its k-th distance, and a sum above the
 // bound cannot reach the result.  The results do not depend on the timing.
-template <int KR, bool ROWS>
-__global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(KR > 10 ? 3 : 4)))
+template <int KR, bool ROWS, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(KR > 10 ? 3 : 4)))
 void k_band(BandArgs a)
 {
+    constexpr int kMW = NW;
+    constexpr int kMRows = 16 * NW;         // list entries per tile: 4 loader threads a row
+    constexpr int kMBlockQ = NW * kMQ;
+    static_assert(kMRows % 32 == 0, "a tile holds whole 32-row blocks");
     __shared__ uint4 tile[kMRows * 8];
     __shared__ __align__(16) int tile_c[kMRows];     // floor(crow / 2)
     __shared__ uint8_t tile_p[kMRows];               // crow mod 2
@@ -533,7 +537,28 @@ size_t band_scratch_bytes(uint32_t curves, uint64_t n, uint32_t nq)
     return band_layout(curves, n, nq).total;
 }
 
-// Runs the banded search with the query keys already in d_scratch.
+template <int NW>
+static void launch_band(const IndexView &v, uint32_t k, uint32_t nq, const BandArgs &a,
+                        hipStream_t st)
+{
+    const uint32_t blocks = (uint32_t)(((uint64_t)nq + NW * kMQ - 1) / (NW * kMQ)) * v.curves;
+    const dim3 grid(blocks), block(64 * NW);
+    if (v.rows[0]) {
+        if (k == 1) hipLaunchKernelGGL((k_band<1, true, NW>), grid, block, 0, st, a);
+        else if (k <= 4) hipLaunchKernelGGL((k_band<4, true, NW>), grid, block, 0, st, a);
+        else if (k <= 10) hipLaunchKernelGGL((k_band<10, true, NW>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_band<kBandK, true, NW>), grid, block, 0, st, a);
+    } else {
+        if (k == 1) hipLaunchKernelGGL((k_band<1, false, NW>), grid, block, 0, st, a);
+        else if (k <= 4) hipLaunchKernelGGL((k_band<4, false, NW>), grid, block, 0, st, a);
+        else if (k <= 10) hipLaunchKernelGGL((k_band<10, false, NW>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_band<kBandK, false, NW>), grid, block, 0, st, a);
+    }
+}
+
+// Runs the banded search with the query keys already in d_scratch.  w_fixed
+// is the window, or with per-query windows a typical one (the block size
+// follows it).
 hc_status band_search(const IndexView &v, const uint8_t *d_queries, uint32_t nq, uint32_t k,
                       uint32_t w_fixed, const uint32_t *d_w, uint32_t *d_out_ids,
                       uint32_t *d_out_dists, void *d_scratch, size_t scratch_bytes,
@@ -569,19 +594,8 @@ hc_status band_search(const IndexView &v, const uint8_t *d_queries, uint32_t nq,
     hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(kScanThreads), 0, st, a.counts, nc);
     const uint64_t nt = (uint64_t)nq * v.curves;
     hipLaunchKernelGGL(k_band_scatter, dim3((uint32_t)((nt + 255) / 256)), dim3(256), 0, st, a);
-    const uint32_t blocks = (uint32_t)(((uint64_t)nq + kMBlockQ - 1) / kMBlockQ) * v.curves;
-    const dim3 grid(blocks), block(kMThreads);
-    if (v.rows[0]) {
-        if (k == 1) hipLaunchKernelGGL((k_band<1, true>), grid, block, 0, st, a);
-        else if (k <= 4) hipLaunchKernelGGL((k_band<4, true>), grid, block, 0, st, a);
-        else if (k <= 10) hipLaunchKernelGGL((k_band<10, true>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_band<kBandK, true>), grid, block, 0, st, a);
-    } else {
-        if (k == 1) hipLaunchKernelGGL((k_band<1, false>), grid, block, 0, st, a);
-        else if (k <= 4) hipLaunchKernelGGL((k_band<4, false>), grid, block, 0, st, a);
-        else if (k <= 10) hipLaunchKernelGGL((k_band<10, false>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_band<kBandK, false>), grid, block, 0, st, a);
-    }
+    if (w_fixed < kBandWideW) launch_band<4>(v, k, nq, a, st);
+    else launch_band<8>(v, k, nq, a, st);
     hipLaunchKernelGGL(k_band_merge, dim3(nq), dim3(64), 0, st, a);
     return last_hip();
 }

@@ -32,7 +32,7 @@
 namespace hc {
 
 constexpr int kKR = 16;                 // longest register list (k <= 16)
-constexpr double kBandShare = 6.0;      // windows per list entry from which to band
+constexpr double kBandShare = 3.5;      // windows per list entry from which to band
                                         // (MI355X, n = 1e7, nq = 1e5: break-even at w ~ 512)
 constexpr uint32_t kMaxSetSlots = 4096; // union capacity of the set kernel
 constexpr int kIdBatch = 16;            // set kernel: ids loaded before inserting
