@@ -228,7 +228,9 @@ hc_status hc_search_encoded(const hc_index *idx, const uint8_t *d_queries, uint3
  *                  query keeps the entries inside its own window (for large
  *                  batches with large windows, where one list entry lies in
  *                  many windows).  k <= 16.
- *  HC_PATH_AUTO:   banded when 2 w nq >= 3.5 n (w = w_fixed or the hint), k <= 16
+ *  HC_PATH_AUTO:   banded when 2 w nq >= 3.5 n (w = w_fixed or the hint), the
+ *                  batch makes at least 512 blocks (nq / 128 or nq / 256 per
+ *                  curve, times curves), k <= 16
  *                  and the scratch holds hc_search_scratch_bytes; else gather.
  * hc_search_encoded is hc_search_encoded_ex with HC_PATH_AUTO. */
 #define HC_PATH_AUTO 0u

@@ -556,6 +556,12 @@ static void launch_band(const IndexView &v, uint32_t k, uint32_t nq, const BandA
     }
 }
 
+uint64_t band_blocks(uint32_t curves, uint32_t nq, uint32_t w)
+{
+    const uint64_t q = w < kBandWideW ? 4 * kMQ : 8 * kMQ;
+    return ((uint64_t)nq + q - 1) / q * curves;
+}
+
 // Runs the banded search with the query keys already in d_scratch.  w_fixed
 // is the window, or with per-query windows a typical one (the block size
 // follows it).

@@ -103,6 +103,7 @@ hc_status encode_rows(const IndexView &v, const uint8_t *rows, uint64_t nrows, K
 
 // Banded search (hc_band.hip), query keys already at the start of d_scratch.
 size_t band_scratch_bytes(uint32_t curves, uint64_t n, uint32_t nq);
+uint64_t band_blocks(uint32_t curves, uint32_t nq, uint32_t w);   // blocks of its main kernel
 hc_status band_search(const IndexView &v, const uint8_t *d_queries, uint32_t nq, uint32_t k,
                       uint32_t w_fixed, const uint32_t *d_w, uint32_t *d_out_ids,
                       uint32_t *d_out_dists, void *d_scratch, size_t scratch_bytes,

@@ -33,6 +33,7 @@ namespace hc {
 
 constexpr int kKR = 16;                 // longest register list (k <= 16)
 constexpr double kBandShare = 3.5;      // windows per list entry from which to band
+constexpr double kBandMinBlocks = 512;  // banded blocks from which to band (2 per CU)
                                         // (MI355X, n = 1e7, nq = 1e5: break-even at w ~ 512)
 constexpr uint32_t kMaxSetSlots = 4096; // union capacity of the set kernel
 constexpr int kIdBatch = 16;            // set kernel: ids loaded before inserting
@@ -320,10 +321,13 @@ hc_status hc_search_choose_path(const hc_index *idx, uint32_t nq, uint32_t k, ui
 {
     if (!idx || !path) return HC_ERR_INVALID;
     // banded when each list entry lies in enough windows of the batch (the rows
-    // it saves outweigh the entries its groups stream outside windows)
+    // it saves outweigh the entries its groups stream outside windows) and the
+    // batch makes enough blocks to fill the device (a small batch spreads each
+    // block over a long stretch of the list, streamed by few blocks)
     const bool shared = 2.0 * (double)w * nq >= kBandShare * (double)idx->v.n;
+    const bool wide = (double)band_blocks(idx->v.curves, nq, w) >= kBandMinBlocks;
     const bool fits = scratch_bytes >= band_scratch_bytes(idx->v.curves, idx->v.n, nq);
-    *path = (shared && fits && k >= 1 && k <= 16) ? HC_PATH_BAND : HC_PATH_GATHER;
+    *path = (shared && wide && fits && k >= 1 && k <= 16) ? HC_PATH_BAND : HC_PATH_GATHER;
     return HC_OK;
 }
 
