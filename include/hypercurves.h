@@ -294,7 +294,7 @@ hc_status hc_search_uneven(const hc_index *idx, const uint8_t *d_queries, uint32
 /* Parity / inspection exports: the same kernels, stopping early           */
 /* ---------------------------------------------------------------------- */
 
-/* Keys of every row and curve (Sec. 2.2.1, Alg. 1 lines 4-9): d_keys receives
+/* Keys of every row and curve (Sec. 2.2.1, the keys of Alg. 1): d_keys receives
  * nrows x curves keys as {hi, lo} pairs, laid out [row][curve]. */
 hc_status hc_encode_keys(const hc_params *p, const uint8_t *d_rows, uint64_t nrows,
                          uint64_t *d_keys, hc_stream stream);

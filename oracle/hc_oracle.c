@@ -16,9 +16,8 @@
  *                                 Butz-type scheme, here in the transposed
  *                                 form published by J. Skilling, "Programming
  *                                 the Hilbert curve", AIP Conf. Proc. 707, 2004)
- *   hco_zorder_encode / _decode   the Z-order (Morton) key used as a comparison
- *                                 curve (the space-filling curves of Sec. 2.2:
- *                                 coordinate bits interleaved, no rotation)
+ *   hco_zorder_encode / _decode   the Z-order key, a comparison curve: the
+ *                                 coordinates' bits intercalated (Sec. 2.2.1)
  *   hco_keys, hco_keys_ex         Alg. 1 / Alg. 2 projection + key
  *   hco_build                     Alg. 1 (sorted <key, id> list per curve)
  *   hco_lower_bound, hco_positions  binary search of the query key
@@ -32,7 +31,7 @@
  * GPU library):
  *   - key bit layout: transposed form, most significant bit first, for bit
  *     level b = m-1 .. 0 and for dim i = 0 .. d-1 emit bit b of X[i];
- *   - the "depth closest vectors to key" of Alg. 2 are a positional window:
+ *   - the probe-depth entries nearest the key in Alg. 2 are a positional window:
  *     w list entries with key < qkey and w entries with key >= qkey (the
  *     half-list model of Sec. 4.2), each half clamped to the list ends;
  *   - lists are ordered by (key, id); the union is a set; the result is
@@ -160,11 +159,10 @@ int hco_hilbert_decode(const uint64_t *hi, const uint64_t *lo, int64_t npts,
     return 0;
 }
 
-/* Z-order key: the coordinates' bits interleaved with no rotation or
- * reflection (G. M. Morton, 1966), in the same bit layout as the Hilbert key:
- * most significant level first, dim 0 first within a level.  It is the
- * curve the Hilbert curve is compared with (Sec. 2.2): both visit every cell
- * once, but only the Hilbert curve moves between adjacent cells. */
+/* Z-order key: the coordinates' bits intercalated (Sec. 2.2.1; G. M. Morton,
+ * 1966), in the same bit layout as the Hilbert key: most significant level
+ * first, dim 0 first within a level.  Both curves visit every cell once
+ * (Sec. 2.2.1), but only the Hilbert curve moves between adjacent cells. */
 int hco_zorder_encode(const uint32_t *coords, int64_t npts, int n, int bits,
                       uint64_t *hi, uint64_t *lo)
 {
