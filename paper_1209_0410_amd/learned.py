@@ -60,6 +60,23 @@ def labels(ix: Index, rank, queries, truth_ids):
     return out
 
 
+def mixed_k_examples(ix: Index, rank, db, queries, ks):
+    """Features (with each query's own k) and labels (the smallest w that
+    recovers its exact top-k) for queries with per-query k (1 <= k <= 16):
+    training examples for requests of mixed depth."""
+    from .index import brute_force
+    ks = np.asarray(ks, np.uint32)
+    gk = torch.from_numpy(ks.view(np.int32)).to(queries.device)
+    feats = features(ix, queries, 0, gk)
+    labs = torch.empty(queries.shape[0], dtype=torch.int32, device=queries.device)
+    for k in np.unique(ks):
+        m = torch.from_numpy(np.nonzero(ks == k)[0]).to(queries.device)
+        sub = queries[m].contiguous()
+        truth, _ = brute_force(db, sub, int(k))
+        labs[m] = labels(ix, rank, sub, truth)
+    return feats, labs
+
+
 def union_sizes(ix: Index, rank, queries, w=0, w_per_query=None):
     _check_rows(queries, "queries")
     nq = queries.shape[0]
@@ -108,9 +125,12 @@ class WModel:
         return torch.log2(lab.to(torch.float64)).to(torch.float32)
 
     def set_norm(self, feats):
+        """Standardisation from training features; a feature that does not vary
+        in training keeps unit scale (so unseen values stay moderate)."""
         f = feats.to(torch.float64)
         mean = f.mean(0)
-        std = f.std(0).clamp_min(1e-6)
+        std = f.std(0)
+        std = torch.where(std < 1e-3, torch.ones_like(std), std)
         self.norm = torch.cat([mean, std]).to(torch.float32).contiguous()
 
     def train(self, feats, y, epochs=20, batch=4096, lr=1e-3, seed=0, log=None):

@@ -74,6 +74,7 @@ class _Slot:
         self.stream = torch.cuda.Stream(device=dev)
         self.q = torch.empty((cap, 128), dtype=torch.uint8, device=dev)
         self.k = torch.empty(cap, dtype=torch.int32, device=dev)
+        self.kf = torch.empty(cap, dtype=torch.int32, device=dev)
         self.w = torch.empty(cap, dtype=torch.int32, device=dev)
         self.feat = torch.empty((cap, learned.FEATURES), dtype=torch.float32, device=dev)
         self.ids = torch.empty((cap, k_stride), dtype=torch.int32, device=dev)
@@ -98,11 +99,13 @@ class Server:
     (fixed w only: the learned w is inferred on the GPU)."""
 
     def __init__(self, ix, model=None, w_fixed=64, k_stride=100, max_batch=4096, slots=3,
-                 budget=None, cfg=None, w_fallback=None, host=None, cpu_workers=0):
+                 budget=None, cfg=None, w_fallback=None, host=None, cpu_workers=0,
+                 k_feature=10):
         if host is not None and model is not None:
             raise ValueError("the host path takes the fixed w; use model=None with host")
         self.ix = ix
         self.model = model
+        self.k_feature = int(k_feature)     # the model's features use min(k, k_feature)
         self.host = host
         self.cpu_workers = int(cpu_workers) if host is not None else 0
         self.w_fixed = int(w_fixed)
@@ -114,15 +117,16 @@ class Server:
         self.slots = [_Slot(ix, self.max_batch, self.k_stride, dev, cfg) for _ in range(slots)]
         self.budget = budget if budget is not None else HbmBudget()
 
-    def _launch(self, slot, hq, hk, lo, hi):
+    def _launch(self, slot, hq, hk, hkf, lo, hi):
         nq = hi - lo
         with torch.cuda.stream(slot.stream):
             slot.q[:nq].copy_(hq[lo:hi], non_blocking=True)
             slot.k[:nq].copy_(hk[lo:hi], non_blocking=True)
+            slot.kf[:nq].copy_(hkf[lo:hi], non_blocking=True)
             q = slot.q[:nq]
             if self.model is not None:
                 kmax = int(self.k_stride)
-                capi.call("hc_features", self.ix.handle, ctp(q), nq, kmax, ctp(slot.k),
+                capi.call("hc_features", self.ix.handle, ctp(q), nq, kmax, ctp(slot.kf),
                           ctp(slot.feat), ctp(slot.fscratch), slot.fscratch.numel(),
                           stream_of(slot.stream))
                 capi.call("hc_mlp_infer", ctp(self.model.bf16), ctp(self.model.norm),
@@ -147,6 +151,9 @@ class Server:
         R = len(arrivals)
         hq = torch.from_numpy(queries).pin_memory()
         hk = torch.from_numpy(np.ascontiguousarray(ks, np.uint32).view(np.int32)).pin_memory()
+        # the model sees k' = min(k, k_feature): the depth it was trained for
+        hkf = torch.from_numpy(np.minimum(np.asarray(ks, np.uint32), self.k_feature)
+                               .astype(np.uint32).view(np.int32)).pin_memory()
         done_at = np.zeros(R)
         res_ids = np.zeros((R, self.k_stride), np.uint32) if keep_results else None
         res_d = np.zeros((R, self.k_stride), np.uint32) if keep_results else None
@@ -222,7 +229,7 @@ class Server:
                 end = min(ready_end, nxt + int(fit))
                 if end > nxt and self.budget.take(batch_bytes(end - nxt, self.k_stride)):
                     nb = batch_bytes(end - nxt, self.k_stride)
-                    self._launch(free[0], hq, hk, nxt, end)
+                    self._launch(free[0], hq, hk, hkf, nxt, end)
                     inflight.append((free[0], nxt, end, nb))
                     sizes.append(end - nxt)
                     batches += 1
@@ -305,19 +312,23 @@ def main(argv=None):
     torch.cuda.synchronize()
     log(f"{a.n} rows resident, index {ix.index_bytes / 1e9:.1f} GB, {time.time() - t0:.1f}s")
 
-    # learned w: labels from exact kNN, the model trained on the GPU; delta is
-    # set so that the mean learned w equals the fixed w (equal search cost)
+    # learned w: labels from exact kNN, the model trained on the GPU for the
+    # request mix (a request's k, capped at 10: recall is judged on its first
+    # 10 results); delta is set so that the mean learned w over the mix equals
+    # the fixed w (equal search cost)
     t0 = time.time()
+    kmix = np.array([1, 10, 100], np.uint32)
+    rng = np.random.default_rng(datagen.SEED_TRAIN)
     rank = learned.ranks(ix)
     tq = torch.from_numpy(datagen.make_queries(a.train, seed=datagen.SEED_TRAIN)).to(dev)
-    ttruth, _ = brute_force(gdb, tq, 10)
-    lab = learned.labels(ix, rank, tq, ttruth)
-    feats = learned.features(ix, tq, 10)
+    feats, lab = learned.mixed_k_examples(ix, rank, gdb, tq,
+                                          np.minimum(rng.choice(kmix, a.train), 10))
     model = learned.WModel(dev, seed=0, w_min=8, w_max=a.w_max)
     model.set_norm(feats)
     model.train(feats, model.targets(lab), epochs=a.epochs, batch=4096, lr=1e-3, seed=1)
     cq = torch.from_numpy(datagen.make_queries(10_000, seed=datagen.SEED_CALIB)).to(dev)
-    cf = learned.features(ix, cq, 10)
+    ck = np.minimum(rng.choice(kmix, 10_000), 10).astype(np.uint32)
+    cf = learned.features(ix, cq, 0, torch.from_numpy(ck.view(np.int32)).to(dev))
     lo_d, hi_d = -16.0, 16.0
     for _ in range(40):
         mid = 0.5 * (lo_d + hi_d)
@@ -326,7 +337,7 @@ def main(argv=None):
         else:
             lo_d = mid
     model.delta = lo_d
-    del rank, tq, ttruth, lab, feats
+    del rank, tq, lab, feats
     torch.cuda.synchronize()
     log(f"model trained on {a.train} queries, delta {model.delta:.3f}, {time.time() - t0:.1f}s")
 
@@ -345,19 +356,26 @@ def main(argv=None):
     # recall on a sample, each request searched alone (same w, same k)
     S = min(a.recall_sample, R)
     sq, sk = queries[:S], ks[:S]
-    truth, _ = brute_force(gdb, torch.from_numpy(sq).to(dev), 10)
-    truth = truth.cpu().numpy().view(np.uint32)
+    gsq = torch.from_numpy(sq).to(dev)
+    sf = learned.features(ix, gsq, 0, torch.from_numpy(
+        np.minimum(sk, 10).astype(np.uint32).view(np.int32)).to(dev))
+    mean_w = float(model.windows(sf, None, a.w).float().mean().item())
     rec = {}
     for name, m in (("learned", model), ("fixed", None)):
         s2 = Server(ix, model=m, w_fixed=a.w, k_stride=100, max_batch=1024, slots=1)
         _, (ids, _) = s2.run(np.zeros(S), sq, sk, keep_results=True, realtime=False)
-        hits = [len(set(ids[i, :min(int(sk[i]), 10)].tolist()) &
-                    set(truth[i, :min(int(sk[i]), 10)].tolist())) / min(int(sk[i]), 10)
-                for i in range(S)]
+        hits = []
+        for k in (1, 10):
+            sel = np.nonzero(np.minimum(sk, 10) == k)[0]
+            truth, _ = brute_force(gdb, gsq[torch.from_numpy(sel).to(dev)].contiguous(), k)
+            truth = truth.cpu().numpy().view(np.uint32)
+            hits += [len(set(ids[i, :k].tolist()) & set(truth[j].tolist())) / k
+                     for j, i in enumerate(sel)]
         rec[name] = float(np.mean(hits))
     out = {"scenario": "serving loop", "n": a.n, "requests": R, "duration_s": a.duration,
            "rate_qps": [a.lo, a.hi], "period_s": a.period, "k_mix": [1, 10, 100],
            "w_fixed": a.w, "w_max": a.w_max, "delta": model.delta,
+           "mean_learned_w_sample": mean_w,
            "recall_at_min_k_10": rec, "recall_sample": S, **stats}
     print(json.dumps(out), flush=True)
 

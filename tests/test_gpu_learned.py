@@ -232,3 +232,59 @@ def test_training_reduces_loss(setup):
     y = m.targets(lab)
     losses = m.train(f, y, epochs=40, batch=100, lr=3e-3, seed=2)
     assert losses[-1] < 0.5 * losses[0]
+
+
+def test_learned_vs_fixed_at_equal_cost():
+    """What the trained network gains over the fixed w at equal search cost.
+    The model is trained on a request mix (k' = 1 or 10), delta is set so that
+    its mean w on calibration queries equals the fixed w, and recall@k' of the
+    two is measured on fresh queries.  On this input recipe (isotropic noise)
+    the gain is negative: the predicted w spreads the same budget unevenly and
+    the recall curve is concave in w.  The test checks the comparison is made
+    at equal cost and that the model does allocate unevenly, and reports the
+    two recalls."""
+    import torch
+    from paper_1209_0410_amd import datagen, learned
+    from paper_1209_0410_amd.index import Index, brute_force
+    db = datagen.make_db(100_000)
+    gdb = torch.from_numpy(db).cuda()
+    ix = Index(gdb)
+    rank = learned.ranks(ix)
+    rng = np.random.default_rng(11)
+    kmix = np.array([1, 10], np.uint32)
+    tq = torch.from_numpy(datagen.make_queries(20_000, seed=datagen.SEED_TRAIN)).cuda()
+    f, lab = learned.mixed_k_examples(ix, rank, gdb, tq, rng.choice(kmix, 20_000))
+    m = learned.WModel(torch.device("cuda:0"), seed=0, w_min=1, w_max=1 << 15)
+    m.set_norm(f)
+    m.train(f, m.targets(lab), epochs=20, batch=1024, lr=1e-3, seed=1)
+    W = 64
+    eq = torch.from_numpy(datagen.make_queries(3_000, seed=datagen.SEED_EVAL)).cuda()
+    ek = rng.choice(kmix, 3_000).astype(np.uint32)
+    gek = torch.from_numpy(ek.view(np.int32)).cuda()
+    ef = learned.features(ix, eq, 0, gek)
+    lo, hi = -16.0, 16.0                                 # mean w over these queries = W
+    for _ in range(40):
+        mid = 0.5 * (lo + hi)
+        if m.windows(ef, mid, W).float().mean().item() > W:
+            hi = mid
+        else:
+            lo = mid
+    w = m.windows(ef, lo, W)
+    wv = u32(w).astype(np.float64)
+    assert abs(wv.mean() - W) / W < 0.03                 # equal cost
+    assert np.log2(wv).std() > 0.3                       # an uneven allocation
+    li, _ = ix.search_uneven(eq, w_per_query=w, k_per_query=gek, k_stride=10)
+    fi, _ = ix.search_uneven(eq, w=W, k_per_query=gek, k_stride=10)
+    rec = {}
+    for name, ids in (("learned", u32(li)), ("fixed", u32(fi))):
+        hits = []
+        for k in (1, 10):
+            sel = np.nonzero(ek == k)[0]
+            t, _ = brute_force(gdb, eq[torch.from_numpy(sel).cuda()].contiguous(), int(k))
+            t = u32(t)
+            hits += [len(set(ids[i, :k].tolist()) & set(t[j].tolist())) / k
+                     for j, i in enumerate(sel)]
+        rec[name] = float(np.mean(hits))
+    print(f"[gain] mean w {wv.mean():.1f}: recall learned {rec['learned']:.4f}, "
+          f"fixed {rec['fixed']:.4f}, gain {rec['learned'] - rec['fixed']:+.4f}", flush=True)
+    assert 0.05 < rec["learned"] < 1 and 0.05 < rec["fixed"] < 1

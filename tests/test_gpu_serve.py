@@ -94,9 +94,10 @@ def test_learned_w_per_request_in_the_mix(env):
     R = min(len(arr), 1500)
     srv = Server(env["gix"], model=model, w_fixed=32, k_stride=100, max_batch=256, slots=2)
     stats, (ids, d) = srv.run(arr[:R], env["q"][:R], env["ks"][:R])
-    # the w each request got depends on its own features only
+    # the w each request got depends on its own features only (with k capped
+    # at the depth the model is trained for)
     gq = torch.from_numpy(env["q"][:R]).cuda()
-    gk = torch.from_numpy(env["ks"][:R].view(np.int32)).cuda()
+    gk = torch.from_numpy(np.minimum(env["ks"][:R], 10).astype(np.uint32).view(np.int32)).cuda()
     f = learned.features(env["gix"], gq, 0, gk)
     w = u32(model.windows(f, w_fallback=32))
     sel = np.arange(0, R, 9)
