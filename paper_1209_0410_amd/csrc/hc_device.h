@@ -137,7 +137,7 @@ __device__ inline void merge_distinct(const uint64_t *a, uint32_t na, const uint
     for (; o < k; o++) out[o] = kNone;
 }
 
-constexpr int kBuf = 1024;   // LDS buffer of the k > 16 top-k
+constexpr int kBuf = 512;    // LDS buffer of the k > 16 top-k (entries, a power of two)
 
 // LDS of one wavefront's top-k for k > 16.
 struct TopKShared {

@@ -134,10 +134,11 @@ __device__ inline void run_item(const UnevenArgs &a, uint32_t q, uint32_t j, uin
 
 // Persistent work loop; every wavefront exits once the counter passes the
 // item count.  BIG: some k may exceed 16 (needs the LDS top-k).
-// BIG needs 12 KiB of LDS per wavefront, which caps it near 3 waves per SIMD
-// anyway; the register budget follows.
+// Both forms run 4 waves per SIMD: with the 512-entry LDS buffer BIG takes
+// about 8 KiB of LDS per wavefront, so 16 wavefronts fit in a CU's LDS; the few
+// registers BIG spills at this budget cost less than the lost occupancy.
 template <bool BIG>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BIG ? 3 : 4)))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
 void k_items(UnevenArgs a)
 {
     __shared__ WindowSet ws;
