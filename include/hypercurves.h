@@ -244,10 +244,12 @@ hc_status hc_search_encoded_ex(const hc_index *idx, const uint8_t *d_queries, ui
                                size_t scratch_bytes, uint32_t path, hc_stream stream);
 
 /* Row store: for the banded path, each curve's rows copied in list order
- * (stored as 127 - x, the form the matrix products take) with their crow =
- * sum x (x - 256).  The banded search then streams contiguous memory instead
- * of gathering rows by id.  It trades memory for locality: curves * n * 132 B
- * (10.6 GB at n = 10^7).  Results are unchanged.
+ * (stored as 127 - x, the form the matrix products take) with floor(crow / 2)
+ * and crow mod 2 for crow = sum x (x - 256), and the list's ids, each curve
+ * padded to a multiple of 256 entries.  The banded search then copies its
+ * tiles from contiguous memory straight into LDS instead of gathering rows by
+ * id.  It trades memory for locality: about curves * n * 137 B (11.0 GB at
+ * n = 10^7).  Results are unchanged.
  *
  * hc_rowstore_bytes: bytes of the store.  hc_rowstore_build: fills d_rows
  * (caller-owned device memory, 256-byte aligned, at least those bytes) from

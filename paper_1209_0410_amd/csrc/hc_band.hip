@@ -21,6 +21,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "hc_device.h"
 #include "hc_scan.h"
@@ -163,7 +164,7 @@ __device__ inline int list_bound(const uint64_t (&L)[KR], int cq)
 // bound is safe: a curve's list holds k distinct candidates of the union, so
 // the final k-th distance is at most its k-th distance, and a sum above the
 // bound cannot reach the result.  The results do not depend on the timing.
-template <int KR, bool ROWS, int NW>
+template <int KR, int NW>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(KR > 10 ? 3 : 4)))
 void k_band(BandArgs a)
 {
@@ -243,18 +244,22 @@ void k_band(BandArgs a)
 #pragma unroll
     for (int i = 0; i < KR; i++) L[i] = kNone;
     // bound from the other curves, in the sum's terms (sum = distance - cq)
+    // It is re-read every 8 tiles and taken into account one tile later, so
+    // that the read's latency hides behind a tile of work.
     int ext = INT32_MAX;
+    uint32_t bread = kEmpty;
     auto read_bound = [&]() {
-        if (live) {
-            const uint32_t b = __hip_atomic_load(a.bound + q, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-            if (b != kEmpty) {
-                const int e = (int)b - cq;
-                ext = e < ext ? e : ext;
-            }
+        bread = live ? __hip_atomic_load(a.bound + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                     : kEmpty;
+    };
+    auto take_bound = [&]() {
+        if (bread != kEmpty) {
+            const int e = (int)bread - cq;
+            ext = e < ext ? e : ext;
         }
     };
     read_bound();
+    take_bound();
 
     // Tiles are taken from the middle of the union outwards: the entries
     // nearest the queries' places come first and fill the lists with close
@@ -270,12 +275,10 @@ void k_band(BandArgs a)
         return U0 + j * kMRows;
     };
 
-    // loader: thread t fills 32 bytes (parts 2f, 2f + 1) of tile row t / 4.
-    // From the database, the ids run two tiles ahead of the rows, the rows one
-    // tile ahead of the matrix work; from the row store (the rows of this
-    // curve in list order, already 127 - x, and their crow) rows, crow and ids
-    // all come one tile ahead.  Rows past the union (the last tile's tail)
-    // read a valid row: they lie outside every window and are never offered.
+    // loader: thread t fills 32 bytes (parts 2f, 2f + 1) of tile row t / 4;
+    // the ids run two tiles ahead of the rows, the rows one tile ahead of the
+    // matrix work.  Rows past the union (the last tile's tail) read a valid
+    // row: they lie outside every window and are never offered.
     const uint32_t *ids = a.v.ids[c];
     const uint32_t lr = (uint32_t)tid >> 2, lf = (uint32_t)tid & 3;
     auto load_id = [&](uint32_t i) -> uint32_t {
@@ -283,47 +286,19 @@ void k_band(BandArgs a)
         return e < U1 ? ids[e] : kEmpty;
     };
     uint4 x0 = make_uint4(0, 0, 0, 0), x1 = x0;
-    int xcrow = 0;
     auto load_row = [&](uint32_t id) {
         const uint64_t r = id != kEmpty ? id : 0u;
         const uint4 *src = reinterpret_cast<const uint4 *>(a.v.db + r * kDim) + 2 * lf;
         x0 = src[0];
         x1 = src[1];
     };
-    uint32_t xid = kEmpty, id_next = kEmpty;
-    auto load_stored = [&](uint32_t i) {
-        const uint64_t e = (uint64_t)tile_start(i) + lr;
-        const uint64_t r = e < U1 ? e : 0u;
-        const uint4 *src = reinterpret_cast<const uint4 *>(a.v.rows[c] + r * kDim) + 2 * lf;
-        x0 = src[0];
-        x1 = src[1];
-        if (lf == 0) {
-            xcrow = a.v.crow[c][r];
-            xid = e < U1 ? ids[e] : kEmpty;
-        }
-    };
-    if constexpr (ROWS) {
-        if (T > 0) load_stored(0);
-    } else {
-        xid = T > 0 ? load_id(0) : kEmpty;
-        id_next = T > 1 ? load_id(1) : kEmpty;
-        if (T > 0) load_row(xid);
-    }
+    uint32_t xid = T > 0 ? load_id(0) : kEmpty;
+    uint32_t id_next = T > 1 ? load_id(1) : kEmpty;
+    if (T > 0) load_row(xid);
 
     for (uint32_t i = 0; i < T; i++) {
         const uint32_t t0 = tile_start(i);
-        if constexpr (ROWS) {   // publish the fetched rows
-            __syncthreads();
-            tile[mslot(lr, 2 * lf)] = x0;
-            tile[mslot(lr, 2 * lf + 1)] = x1;
-            if (lf == 0) {
-                tile_c[lr] = xcrow >> 1;
-                tile_p[lr] = (uint8_t)(xcrow & 1);
-                tile_id[lr] = xid;
-            }
-            __syncthreads();
-            if (i + 1 < T) load_stored(i + 1);
-        } else {
+        {
             uint32_t xx = 0, sx = 0;
             const uint32_t parts[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
 #pragma unroll
@@ -344,14 +319,15 @@ void k_band(BandArgs a)
                 tile_p[lr] = (uint8_t)(crow & 1);
                 tile_id[lr] = xid;
             }
+            if ((i & 7) == 0 && i) take_bound();
             __syncthreads();
+            if ((i & 7) == 7) read_bound();
             if (i + 1 < T) {
                 xid = id_next;
                 load_row(xid);
             }
             if (i + 2 < T) id_next = load_id(i + 2);
         }
-        if ((i & 7) == 7) read_bound();
         if (!(t0 < u1 && (uint64_t)t0 + kMRows > u0)) continue;       // wavefront-uniform
 
         // this lane's bound: its list, the other half's list, the other curves
@@ -419,12 +395,16 @@ void k_band(BandArgs a)
                         v4i{(int)av.x, (int)av.y, (int)av.z, (int)av.w}, bq[s], acc, 0, 0, 0);
                 }
             }
+            int hm[4];
+#pragma unroll
+            for (int g = 0; g < 4; g++)
+                hm[g] = std::min(std::min(acc[4 * g], acc[4 * g + 1]),
+                                 std::min(acc[4 * g + 2], acc[4 * g + 3]));
+            if (std::min(std::min(hm[0], hm[1]), std::min(hm[2], hm[3])) > hb) continue;
 #pragma unroll
             for (int g = 0; g < 4; g++) {
                 const uint32_t r0 = rb * 32 + 8 * g + 4 * h;
-                const int hmin = std::min(std::min(acc[4 * g], acc[4 * g + 1]),
-                                          std::min(acc[4 * g + 2], acc[4 * g + 3]));
-                if (hmin <= hb) {       // rare once the lists are full
+                if (hm[g] <= hb) {       // rare once the lists are full
 #pragma unroll
                     for (int j = 0; j < 4; j++) {
                         if (acc[4 * g + j] <= hb && r0 + j - rlo < rhi - rlo) {
@@ -440,6 +420,372 @@ void k_band(BandArgs a)
     }
 
     // lane qn takes the other half's list (rows of one list: ids distinct)
+#pragma unroll
+    for (int i = 0; i < KR; i++) {
+        const uint64_t o = shfl_xor_u64(L[i], 32);
+        if (h == 0 && o < L[KR - 1]) {
+#pragma unroll
+            for (int j = KR - 1; j > 0; j--)
+                L[j] = o < L[j - 1] ? L[j - 1] : (o < L[j] ? o : L[j]);
+            L[0] = o < L[0] ? o : L[0];
+        }
+    }
+    if (live && h == 0) {
+        uint64_t *out = a.partial + ((uint64_t)q * C + c) * a.k;
+        uint64_t kth = kNone;
+#pragma unroll
+        for (int i = 0; i < KR; i++) {
+            if ((uint32_t)i < a.k) out[i] = L[i];
+            if ((uint32_t)i == a.k - 1) kth = L[i];
+        }
+        if (kth != kNone) atomicMin(a.bound + q, (uint32_t)(kth >> 32));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Banded search from the row store, tiles copied straight into LDS.
+//
+// The same work and the same results as k_band, but a tile's rows, their
+// floor(crow / 2), crow mod 2 and list ids come from the row store by LDS DMA
+// (global_load_lds_dwordx4: lane l of one instruction writes its 16 bytes at
+// the instruction's LDS base + 16 l).  No registers hold a tile on its way,
+// so kStages tiles are in LDS at once: while tile i is worked on, tiles
+// i + 1 .. i + kStages - 2 are in flight, and tile i + kStages - 1 is issued
+// into the stage tile i - 1 used; one barrier per tile.  Tiles are aligned to
+// their size in the list (the row store is padded to a multiple of 256
+// entries), which keeps every 16-byte copy aligned and inside the store.
+//
+// The compiler does not follow LDS DMA closely enough (it would wait for
+// every copy in flight before any LDS read), so the reads of staged data are
+// ds_read instructions with explicit lgkmcnt waits, and each wavefront counts
+// its own copies for the vmcnt waits.
+// ---------------------------------------------------------------------------
+constexpr int kStages = 3;
+
+template <int NW>
+struct BandStage {
+    static constexpr int R = 16 * NW;   // list entries per tile
+    uint4 rows[R * 8];                   // 127 - x, 16-byte parts at mslot(r, part)
+    int crow2[R];                        // floor(crow / 2)
+    uint32_t rid[R];                     // list ids
+    uint8_t par[R];                      // crow mod 2
+};
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+__device__ inline uint32_t lds_addr(const void *p)
+{
+    return (uint32_t)(uintptr_t)(const lds_void *)p;
+}
+
+// 16 bytes per lane from global memory to LDS at lds + 16 * lane
+__device__ inline void dma16(const void *g, void *lds)
+{
+    __builtin_amdgcn_global_load_lds(g, (lds_void *)lds, 16, 0, 0);
+}
+
+// 4 bytes per lane from global memory to LDS at lds + 4 * lane
+__device__ inline void dma4(const void *g, void *lds)
+{
+    __builtin_amdgcn_global_load_lds(g, (lds_void *)lds, 4, 0, 0);
+}
+
+// s_waitcnt vmcnt(n), n <= 9 (expcnt and lgkmcnt left alone)
+__device__ inline void wait_vm(uint32_t n)
+{
+    switch (n) {
+    case 0: __builtin_amdgcn_s_waitcnt(0x0F70); break;
+    case 1: __builtin_amdgcn_s_waitcnt(0x0F71); break;
+    case 2: __builtin_amdgcn_s_waitcnt(0x0F72); break;
+    case 3: __builtin_amdgcn_s_waitcnt(0x0F73); break;
+    case 4: __builtin_amdgcn_s_waitcnt(0x0F74); break;
+    case 5: __builtin_amdgcn_s_waitcnt(0x0F75); break;
+    case 6: __builtin_amdgcn_s_waitcnt(0x0F76); break;
+    case 7: __builtin_amdgcn_s_waitcnt(0x0F77); break;
+    case 8: __builtin_amdgcn_s_waitcnt(0x0F78); break;
+    default: __builtin_amdgcn_s_waitcnt(0x0F79); break;
+    }
+}
+
+template <int OFF>
+__device__ inline v4i lds_b128(uint32_t addr)
+{
+    v4i r;
+    asm volatile("ds_read_b128 %0, %1 offset:%2" : "=v"(r) : "v"(addr), "i"(OFF));
+    return r;
+}
+
+__device__ inline uint32_t lds_b32(uint32_t addr)
+{
+    uint32_t r;
+    asm volatile("ds_read_b32 %0, %1" : "=v"(r) : "v"(addr));
+    return r;
+}
+
+__device__ inline uint32_t lds_u8(uint32_t addr)
+{
+    uint32_t r;
+    asm volatile("ds_read_u8 %0, %1" : "=v"(r) : "v"(addr));
+    return r;
+}
+
+template <int KR, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(KR > 10 ? 3 : 4)))
+void k_band_dma(BandArgs a)
+{
+    constexpr int R = 16 * NW;
+    constexpr int kBlockQ = NW * kMQ;
+    static_assert(R % 32 == 0 && R / 16 >= 1 && NW >= 3, "tile shape");
+    __shared__ BandStage<NW> st[kStages];
+    __shared__ uint32_t bslot[NW][kMQ];
+    __shared__ uint32_t wspan[2][NW];
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int h = lane >> 5, qn = lane & 31;
+    const uint32_t C = a.v.curves;
+    const uint64_t n = a.v.n;
+    const uint32_t groups = (a.nq + kBlockQ - 1) / kBlockQ;
+    const uint32_t grp = blockIdx.x % groups, c = blockIdx.x / groups;
+
+    const uint64_t slot = (uint64_t)grp * kBlockQ + (uint64_t)wv * kMQ + qn;
+    const bool live = slot < a.nq;
+    const uint32_t q = live ? a.order[(uint64_t)c * a.nq + slot] : 0;
+    v4i bq[4];
+    uint32_t qq = 0, sq = 0;
+    {
+        const uint4 *qrow = reinterpret_cast<const uint4 *>(a.queries + (uint64_t)q * kDim);
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+            const uint4 v = live ? qrow[2 * s + h] : make_uint4(0, 0, 0, 0);
+            qq = __builtin_amdgcn_udot4(v.x, v.x, qq, false);
+            qq = __builtin_amdgcn_udot4(v.y, v.y, qq, false);
+            qq = __builtin_amdgcn_udot4(v.z, v.z, qq, false);
+            qq = __builtin_amdgcn_udot4(v.w, v.w, qq, false);
+            sq = __builtin_amdgcn_udot4(v.x, 0x01010101u, sq, false);
+            sq = __builtin_amdgcn_udot4(v.y, 0x01010101u, sq, false);
+            sq = __builtin_amdgcn_udot4(v.z, 0x01010101u, sq, false);
+            sq = __builtin_amdgcn_udot4(v.w, 0x01010101u, sq, false);
+            const uint4 b = xor4(v, 0x80808080u);
+            bq[s] = v4i{(int)b.x, (int)b.y, (int)b.z, (int)b.w};
+        }
+    }
+    qq += __shfl_xor(qq, 32, 64);
+    sq += __shfl_xor(sq, 32, 64);
+    const int cq = (int)(qq - 254u * sq + 4161536u);
+    uint32_t lo, hi;
+    {
+        const uint64_t w = live ? (a.d_w ? a.d_w[q] : a.w_fixed) : 0;
+        const uint64_t p = live ? a.pos[(uint64_t)q * C + c] : 0;
+        lo = live ? (uint32_t)(p > w ? p - w : 0) : 0xFFFFFFFFu;
+        hi = live ? (uint32_t)(p + w < n ? p + w : n) : 0u;
+    }
+    uint32_t u0 = lo, u1 = hi;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint32_t o0 = __shfl_xor(u0, m, 64), o1 = __shfl_xor(u1, m, 64);
+        u0 = o0 < u0 ? o0 : u0;
+        u1 = o1 > u1 ? o1 : u1;
+    }
+    if (lane == 0) {
+        wspan[0][wv] = u0;
+        wspan[1][wv] = u1;
+    }
+    __syncthreads();
+    uint32_t U0 = 0xFFFFFFFFu, U1 = 0;
+#pragma unroll
+    for (int i = 0; i < NW; i++) {
+        U0 = wspan[0][i] < U0 ? wspan[0][i] : U0;
+        U1 = wspan[1][i] > U1 ? wspan[1][i] : U1;
+    }
+
+    uint64_t L[KR];
+#pragma unroll
+    for (int i = 0; i < KR; i++) L[i] = kNone;
+    // bound from the other curves in the sum's terms; later reads come by
+    // DMA into bslot every 8 tiles
+    int ext = INT32_MAX;
+    {
+        const uint32_t b = live ? __hip_atomic_load(a.bound + q, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT)
+                                : kEmpty;
+        if (b != kEmpty) ext = (int)b - cq;
+        // taken now, before any copy is in flight (waiting for it later would
+        // wait for the copies too)
+        asm volatile("" : "+v"(ext)::"memory");
+    }
+
+    // tiles of R entries aligned in the list, middle of the union outwards
+    const uint32_t A0 = U0 < U1 ? (U0 & ~(uint32_t)(R - 1)) : 0u;
+    const uint32_t T = U0 < U1 ? (U1 - A0 + R - 1) / R : 0u;
+    const uint32_t jm = T ? ((U1 - A0) / 2) / R : 0u;
+    const uint32_t nleft = jm, nright = T ? T - 1 - jm : 0u;
+    const uint32_t nboth = nleft < nright ? nleft : nright;
+    auto tile_start = [&](uint32_t i) -> uint32_t {
+        uint32_t j;
+        if (i <= 2 * nboth) j = (i & 1) ? jm + (i + 1) / 2 : jm - i / 2;
+        else j = nright > nleft ? jm + (i - nboth) : jm - (i - nboth);
+        return A0 + j * R;
+    };
+
+    const uint8_t *rows_c = a.v.rows[c];
+    const int *crow2_c = a.v.crow2[c];
+    const uint32_t *rid_c = a.v.rid[c];
+    const uint8_t *par_c = a.v.par[c];
+    // copies per tile issued by this wavefront: two 1 KiB parts of the rows,
+    // and for wavefronts 0, 1, 2 the crow2, id and parity parts
+    const uint32_t gbase = wv < 3 ? 3u : 2u;
+    auto issue = [&](uint32_t j) {
+        BandStage<NW> &S = st[j % kStages];
+        const uint64_t e0 = tile_start(j);
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            const uint32_t m = 2 * wv + k;
+            const uint32_t r = 8 * m + ((uint32_t)lane >> 3);
+            const uint32_t part = ((uint32_t)lane & 7) ^ ((r >> 1) & 7);
+            dma16(rows_c + (e0 + r) * kDim + part * 16, &S.rows[64 * m]);
+        }
+        if (wv == 0) {
+            if (lane < R / 4) dma16(crow2_c + e0 + 4 * lane, &S.crow2[0]);
+        } else if (wv == 1) {
+            if (lane < R / 4) dma16(rid_c + e0 + 4 * lane, &S.rid[0]);
+        } else if (wv == 2) {
+            if (lane < R / 16) dma16(par_c + e0 + 16 * lane, &S.par[0]);
+        }
+    };
+
+    // this lane's A operand parts within a 32-row block: row qn, parts 2s + h
+    uint32_t aoff[4];
+#pragma unroll
+    for (int s4 = 0; s4 < 4; s4++)
+        aoff[s4] = (uint32_t)qn * 128 + ((uint32_t)(2 * s4 + h) ^ (((uint32_t)qn >> 1) & 7)) * 16;
+
+    // Tile i sits in stage i % kStages.  Its copies are complete once at most
+    // the copies of the tiles after it that are in flight (up to kStages - 2
+    // tiles, gbase instructions each) are outstanding; a bound copy, issued
+    // before a tile's copies, only makes that wait longer.  The bound copied
+    // at tile m (m % 8 == 7) is complete at tile m + kStages - 2.
+    static_assert(kStages >= 3 && 3 * (kStages - 2) <= 9, "wait counts");
+    for (uint32_t j = 0; j + 1 < kStages && j < T; j++) issue(j);
+    for (uint32_t i = 0; i < T; i++) {
+        const uint32_t later = std::min<uint32_t>(kStages - 2, T - 1 - i);
+        wait_vm(gbase * later);
+        __builtin_amdgcn_s_barrier();
+        if (i >= 7 + kStages - 2 && ((i - (kStages - 2)) & 7) == 7 && i + 1 < T) {
+            uint32_t b = lds_b32(lds_addr(&bslot[wv][qn]));
+            asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(b));
+            if (live && b != kEmpty) {
+                const int e = (int)b - cq;
+                ext = e < ext ? e : ext;
+            }
+        }
+        const uint32_t t0 = tile_start(i);
+        if (t0 < u1 && (uint64_t)t0 + R > u0) {       // wavefront-uniform
+
+        BandStage<NW> &S = st[i % kStages];
+        const uint32_t rows_l = lds_addr(&S.rows[0]);
+        const uint32_t crow_l = lds_addr(&S.crow2[0]) + 16 * h;
+        const uint32_t rid_l = lds_addr(&S.rid[0]), par_l = lds_addr(&S.par[0]);
+
+        const int own = list_bound(L, cq);
+        int th = own;
+        {
+            const int other = __shfl_xor(own, 32, 64);
+            th = other < th ? other : th;
+            th = ext < th ? ext : th;
+        }
+        const uint32_t rlo = lo > t0 ? std::min<uint32_t>(lo - t0, R) : 0u;
+        const uint32_t rhi = hi > t0 ? std::min<uint32_t>(hi - t0, R) : 0u;
+        if (!live || rlo >= rhi) th = INT32_MIN;
+        int hb = th >> 1;
+        int pend_h = 0;
+        uint32_t pend_r = kNoRow;
+        auto insert_pending = [&]() {
+            uint32_t p = lds_u8(par_l + pend_r), id = lds_b32(rid_l + 4 * pend_r);
+            asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(p), "+v"(id));
+            const int t = 2 * pend_h + (int)p;
+            const uint64_t key = ((uint64_t)(uint32_t)(t + cq) << 32) | id;
+            if (key < L[KR - 1]) {
+#pragma unroll
+                for (int m = KR - 1; m > 0; m--)
+                    L[m] = key < L[m - 1] ? L[m - 1] : (key < L[m] ? key : L[m]);
+                L[0] = key < L[0] ? key : L[0];
+                const int b = list_bound(L, cq);
+                th = b < th ? b : th;
+                hb = th >> 1;
+            }
+            pend_r = kNoRow;
+        };
+        // this lane's A operand addresses and crow2 address in this stage
+        const uint32_t ab0 = rows_l + aoff[0], ab1 = rows_l + aoff[1], ab2 = rows_l + aoff[2],
+                       ab3 = rows_l + aoff[3];
+        // one 32-row block; RB is a compile-time constant, so that the block's
+        // LDS offsets are immediates
+        auto block32 = [&](auto rbc) {
+            constexpr uint32_t RB = decltype(rbc)::value;
+            v4i c0 = lds_b128<RB * 128>(crow_l), c1 = lds_b128<RB * 128 + 32>(crow_l),
+                c2 = lds_b128<RB * 128 + 64>(crow_l), c3 = lds_b128<RB * 128 + 96>(crow_l);
+            v4i a0 = lds_b128<RB * 4096>(ab0), a1 = lds_b128<RB * 4096>(ab1),
+                a2 = lds_b128<RB * 4096>(ab2), a3 = lds_b128<RB * 4096>(ab3);
+            asm volatile("s_waitcnt lgkmcnt(3)" : "+v"(c0), "+v"(c1), "+v"(c2), "+v"(c3), "+v"(a0));
+            v16i acc = v16i{c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w,
+                            c2.x, c2.y, c2.z, c2.w, c3.x, c3.y, c3.z, c3.w};
+            acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, bq[0], acc, 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);     // each product starts as its operand lands
+            asm volatile("s_waitcnt lgkmcnt(2)" : "+v"(a1));
+            acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, bq[1], acc, 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            asm volatile("s_waitcnt lgkmcnt(1)" : "+v"(a2));
+            acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, bq[2], acc, 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(a3));
+            acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a3, bq[3], acc, 0, 0, 0);
+            const int m0 = std::min(std::min(acc[0], acc[1]), acc[2]);
+            const int m1 = std::min(std::min(acc[3], acc[4]), acc[5]);
+            const int m2 = std::min(std::min(acc[6], acc[7]), acc[8]);
+            const int m3 = std::min(std::min(acc[9], acc[10]), acc[11]);
+            const int m4 = std::min(std::min(acc[12], acc[13]), acc[14]);
+            const int mm = std::min(std::min(std::min(m0, m1), m2),
+                                    std::min(std::min(m3, m4), acc[15]));
+            if (mm > hb) return;        // rare once the lists are full
+            int hm[4];
+#pragma unroll
+            for (int g = 0; g < 4; g++)
+                hm[g] = std::min(std::min(acc[4 * g], acc[4 * g + 1]),
+                                 std::min(acc[4 * g + 2], acc[4 * g + 3]));
+#pragma unroll
+            for (int g = 0; g < 4; g++) {
+                const uint32_t r0 = RB * 32 + 8 * g + 4 * h;
+                if (hm[g] <= hb) {
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        if (acc[4 * g + j] <= hb && r0 + j - rlo < rhi - rlo) {
+                            if (pend_r != kNoRow) insert_pending();
+                            pend_h = acc[4 * g + j];
+                            pend_r = r0 + j;
+                        }
+                    }
+                }
+            }
+        };
+        block32(std::integral_constant<uint32_t, 0>{});
+        block32(std::integral_constant<uint32_t, 1>{});
+        if constexpr (R / 32 > 2) {
+            block32(std::integral_constant<uint32_t, 2>{});
+            block32(std::integral_constant<uint32_t, 3>{});
+        }
+        if (pend_r != kNoRow) insert_pending();
+        }
+        if (i + kStages - 1 < T) {
+            // the bound copy goes before the tile's copies, hence the compiler
+            // barrier; stage (i - 1) % kStages is free, every wavefront having
+            // passed this tile's barrier
+            if ((i & 7) == 7 && lane < kMQ) dma4(a.bound + q, &bslot[wv][0]);
+            asm volatile("" ::: "memory");
+            issue(i + kStages - 1);
+        }
+    }
+
 #pragma unroll
     for (int i = 0; i < KR; i++) {
         const uint64_t o = shfl_xor_u64(L[i], 32);
@@ -484,9 +830,11 @@ __global__ __launch_bounds__(64) void k_band_merge(BandArgs a)
 }
 
 // Row store of curve c: 8 lanes per list entry, each 16 bytes of the row
-// (127 - x) and its part of crow, reduced over the 8 lanes.
-__global__ __launch_bounds__(256) void k_rowstore(IndexView v, uint32_t c, uint8_t *rows,
-                                                  int *crow)
+// (127 - x) and its part of crow, reduced over the 8 lanes.  Entries from n
+// to the padded length get zero rows and crow, and no id.
+__global__ __launch_bounds__(256) void k_rowstore(IndexView v, uint32_t c, uint64_t npad,
+                                                  uint8_t *rows, int *crow2, uint8_t *par,
+                                                  uint32_t *rid)
 {
     const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t e = t >> 3;
@@ -494,7 +842,7 @@ __global__ __launch_bounds__(256) void k_rowstore(IndexView v, uint32_t c, uint8
     const bool valid = e < v.n;
     const uint32_t id = valid ? v.ids[c][e] : 0u;
     const uint4 x = valid ? reinterpret_cast<const uint4 *>(v.db + (uint64_t)id * kDim)[part]
-                          : make_uint4(0, 0, 0, 0);
+                          : make_uint4(0x7F7F7F7Fu, 0x7F7F7F7Fu, 0x7F7F7F7Fu, 0x7F7F7F7Fu);
     uint32_t xx = __builtin_amdgcn_udot4(x.x, x.x, 0u, false);
     xx = __builtin_amdgcn_udot4(x.y, x.y, xx, false);
     xx = __builtin_amdgcn_udot4(x.z, x.z, xx, false);
@@ -508,25 +856,39 @@ __global__ __launch_bounds__(256) void k_rowstore(IndexView v, uint32_t c, uint8
         xx += __shfl_xor(xx, m, 64);
         sx += __shfl_xor(sx, m, 64);
     }
-    if (valid) {
+    if (e < npad) {
         reinterpret_cast<uint4 *>(rows + e * kDim)[part] = xor4(x, 0x7F7F7F7Fu);
-        if (part == 0) crow[e] = (int)(xx - 256u * sx);
+        if (part == 0) {
+            const int crow = valid ? (int)(xx - 256u * sx) : 0;
+            crow2[e] = crow >> 1;
+            par[e] = (uint8_t)(crow & 1);
+            rid[e] = valid ? id : kEmpty;
+        }
     }
 }
 
+constexpr uint64_t kRowPad = 256;   // row store entries per curve: a multiple of this
+
 struct RowStoreLayout {
-    size_t rows_off[kMaxCurves], crow_off[kMaxCurves], total;
+    uint64_t npad;
+    size_t rows_off[kMaxCurves], crow_off[kMaxCurves], par_off[kMaxCurves],
+        rid_off[kMaxCurves], total;
 };
 
 static RowStoreLayout rowstore_layout(uint32_t curves, uint64_t n)
 {
     RowStoreLayout L{};
+    L.npad = (n + kRowPad - 1) / kRowPad * kRowPad;
     size_t off = 0;
     for (uint32_t c = 0; c < curves; c++) {
         L.rows_off[c] = off;
-        off = align256(off + (size_t)kDim * n);
+        off = align256(off + (size_t)kDim * L.npad);
         L.crow_off[c] = off;
-        off = align256(off + sizeof(int) * n);
+        off = align256(off + sizeof(int) * L.npad);
+        L.par_off[c] = off;
+        off = align256(off + L.npad);
+        L.rid_off[c] = off;
+        off = align256(off + sizeof(uint32_t) * L.npad);
     }
     L.total = off;
     return L;
@@ -544,15 +906,15 @@ static void launch_band(const IndexView &v, uint32_t k, uint32_t nq, const BandA
     const uint32_t blocks = (uint32_t)(((uint64_t)nq + NW * kMQ - 1) / (NW * kMQ)) * v.curves;
     const dim3 grid(blocks), block(64 * NW);
     if (v.rows[0]) {
-        if (k == 1) hipLaunchKernelGGL((k_band<1, true, NW>), grid, block, 0, st, a);
-        else if (k <= 4) hipLaunchKernelGGL((k_band<4, true, NW>), grid, block, 0, st, a);
-        else if (k <= 10) hipLaunchKernelGGL((k_band<10, true, NW>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_band<kBandK, true, NW>), grid, block, 0, st, a);
+        if (k == 1) hipLaunchKernelGGL((k_band_dma<1, NW>), grid, block, 0, st, a);
+        else if (k <= 4) hipLaunchKernelGGL((k_band_dma<4, NW>), grid, block, 0, st, a);
+        else if (k <= 10) hipLaunchKernelGGL((k_band_dma<10, NW>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_band_dma<kBandK, NW>), grid, block, 0, st, a);
     } else {
-        if (k == 1) hipLaunchKernelGGL((k_band<1, false, NW>), grid, block, 0, st, a);
-        else if (k <= 4) hipLaunchKernelGGL((k_band<4, false, NW>), grid, block, 0, st, a);
-        else if (k <= 10) hipLaunchKernelGGL((k_band<10, false, NW>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_band<kBandK, false, NW>), grid, block, 0, st, a);
+        if (k == 1) hipLaunchKernelGGL((k_band<1, NW>), grid, block, 0, st, a);
+        else if (k <= 4) hipLaunchKernelGGL((k_band<4, NW>), grid, block, 0, st, a);
+        else if (k <= 10) hipLaunchKernelGGL((k_band<10, NW>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_band<kBandK, NW>), grid, block, 0, st, a);
     }
 }
 
@@ -624,18 +986,21 @@ hc_status hc_rowstore_build(hc_index *idx, void *d_rows, size_t bytes, hc_stream
     if (!idx || !d_rows || ((uintptr_t)d_rows & 255)) return HC_ERR_INVALID;
     const RowStoreLayout L = rowstore_layout(idx->v.curves, idx->v.n);
     if (bytes < L.total) return HC_ERR_SIZE;
-    const uint64_t threads = idx->v.n * 8;
+    const uint64_t threads = L.npad * 8;
     uint8_t *base = (uint8_t *)d_rows;
     for (uint32_t c = 0; c < idx->v.curves; c++) {
         hipLaunchKernelGGL(k_rowstore, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0,
-                           (hipStream_t)stream, idx->v, c, base + L.rows_off[c],
-                           (int *)(base + L.crow_off[c]));
+                           (hipStream_t)stream, idx->v, c, L.npad, base + L.rows_off[c],
+                           (int *)(base + L.crow_off[c]), base + L.par_off[c],
+                           (uint32_t *)(base + L.rid_off[c]));
     }
     const hc_status st = last_hip();
     if (st != HC_OK) return st;
     for (uint32_t c = 0; c < idx->v.curves; c++) {
         idx->v.rows[c] = base + L.rows_off[c];
-        idx->v.crow[c] = (const int *)(base + L.crow_off[c]);
+        idx->v.crow2[c] = (const int *)(base + L.crow_off[c]);
+        idx->v.par[c] = base + L.par_off[c];
+        idx->v.rid[c] = (const uint32_t *)(base + L.rid_off[c]);
     }
     return HC_OK;
 }
@@ -645,7 +1010,9 @@ hc_status hc_rowstore_detach(hc_index *idx)
     if (!idx) return HC_ERR_INVALID;
     for (uint32_t c = 0; c < kMaxCurves; c++) {
         idx->v.rows[c] = nullptr;
-        idx->v.crow[c] = nullptr;
+        idx->v.crow2[c] = nullptr;
+        idx->v.par[c] = nullptr;
+        idx->v.rid[c] = nullptr;
     }
     return HC_OK;
 }

@@ -32,10 +32,13 @@ struct IndexView {
     uint16_t perm[kMaxCurves * kDpc];
     uint32_t identity;                        // perm is 16c + j
     uint32_t curve;                           // HC_CURVE_HILBERT or HC_CURVE_ZORDER
-    // optional row store: curve c's rows in list order, stored as 127 - x,
-    // and crow = sum x (x - 256) of each (null when absent)
+    // optional row store, curve c's entries in list order and padded to a
+    // multiple of 256 entries (null when absent): the rows stored as 127 - x,
+    // floor(crow / 2) and crow mod 2 with crow = sum x (x - 256), and the ids
     const uint8_t *rows[kMaxCurves];
-    const int *crow[kMaxCurves];
+    const int *crow2[kMaxCurves];
+    const uint8_t *par[kMaxCurves];
+    const uint32_t *rid[kMaxCurves];
 };
 
 }  // namespace hc
