@@ -271,7 +271,7 @@ def main():
         "sweep": rows,
         "uneven": uneven,
         "f4": f4,
-        "roofline": roofline(head),
+        "roofline": roofline(head, bool(rowstore_bytes)),
     }
     if head is fixed:
         tb, tsrc = counted_traffic(a.n, a.nq, k, w_fix, head["path"])
@@ -345,12 +345,13 @@ def path_name(p):
     return {1: "gather", 2: "band"}[p]
 
 
-def roofline(head):
+def roofline(head, rowstore):
     """Roofline of the search call (hc_search_encoded, timed with HIP events on
     its stream): HBM-bound on the gather path (window ids + distinct rows +
     results per call); on the banded path the distances are int8 matrix-core
     products, 2 x 128 ops per distinct candidate per call, against the dense
-    int8 MFMA peak."""
+    int8 MFMA peak.  With the row store attached the banded kernel is
+    k_band_dma (tiles copied into LDS), else k_band (rows gathered by id)."""
     if head["path"] == "gather":
         return {"bound": "hbm", "achieved": head["alg_GBs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": head["alg_GBs"] / HBM_PEAK_GBS, "traffic": None,
@@ -358,14 +359,15 @@ def roofline(head):
                 "kernel_ms": head["kernel_ms"], "alg_bytes_per_launch": head["alg_bytes"]}
     return {"bound": "mfma", "achieved": head["alg_TOPs"], "peak": MFMA_I8_PEAK_TOPS,
             "unit": "TOP/s", "frac": head["alg_TOPs"] / MFMA_I8_PEAK_TOPS, "traffic": None,
-            "kernel": "k_band with k_band_place/k_scan_excl/k_band_scatter/k_band_merge "
+            "kernel": ("k_band_dma" if rowstore else "k_band")
+                      + " with k_band_place/k_scan_excl/k_band_scatter/k_band_merge "
                       "(hc_search_encoded, banded path)",
             "kernel_ms": head["kernel_ms"],
             "alg_ops_per_launch": head["alg_TOPs"] * 1e12 * head["kernel_ms"] * 1e-3}
 
 
 KERNEL_SOURCES = {"gather": ("k_stream", ("hc_search.hip", "hc_device.h")),
-                  "band": ("k_band", ("hc_band.hip", "hc_search.hip", "hc_device.h",
+                  "band": ("k_band_dma", ("hc_band.hip", "hc_search.hip", "hc_device.h",
                                       "hc_scan.h"))}
 
 

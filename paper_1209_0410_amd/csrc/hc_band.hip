@@ -587,6 +587,8 @@ void k_band_dma(BandArgs a)
         u0 = o0 < u0 ? o0 : u0;
         u1 = o1 > u1 ? o1 : u1;
     }
+    u0 = __builtin_amdgcn_readfirstlane(u0);
+    u1 = __builtin_amdgcn_readfirstlane(u1);
     if (lane == 0) {
         wspan[0][wv] = u0;
         wspan[1][wv] = u1;
@@ -598,6 +600,8 @@ void k_band_dma(BandArgs a)
         U0 = wspan[0][i] < U0 ? wspan[0][i] : U0;
         U1 = wspan[1][i] > U1 ? wspan[1][i] : U1;
     }
+    U0 = __builtin_amdgcn_readfirstlane(U0);
+    U1 = __builtin_amdgcn_readfirstlane(U1);
 
     uint64_t L[KR];
 #pragma unroll
@@ -635,8 +639,8 @@ void k_band_dma(BandArgs a)
     // copies per tile issued by this wavefront: two 1 KiB parts of the rows,
     // and for wavefronts 0, 1, 2 the crow2, id and parity parts
     const uint32_t gbase = wv < 3 ? 3u : 2u;
-    auto issue = [&](uint32_t j) {
-        BandStage<NW> &S = st[j % kStages];
+    auto issue = [&](uint32_t j, uint32_t sj) {
+        BandStage<NW> &S = st[sj];
         const uint64_t e0 = tile_start(j);
 #pragma unroll
         for (int k = 0; k < 2; k++) {
@@ -666,8 +670,10 @@ void k_band_dma(BandArgs a)
     // before a tile's copies, only makes that wait longer.  The bound copied
     // at tile m (m % 8 == 7) is complete at tile m + kStages - 2.
     static_assert(kStages >= 3 && 3 * (kStages - 2) <= 9, "wait counts");
-    for (uint32_t j = 0; j + 1 < kStages && j < T; j++) issue(j);
-    for (uint32_t i = 0; i < T; i++) {
+    for (uint32_t j = 0; j + 1 < kStages && j < T; j++) issue(j, j);
+    uint32_t si = 0, sn = kStages - 1;       // stages of tile i and of tile i + kStages - 1
+    for (uint32_t i = 0; i < T; i++, si = si + 1 == kStages ? 0 : si + 1,
+                  sn = sn + 1 == kStages ? 0 : sn + 1) {
         const uint32_t later = std::min<uint32_t>(kStages - 2, T - 1 - i);
         wait_vm(gbase * later);
         __builtin_amdgcn_s_barrier();
@@ -682,99 +688,96 @@ void k_band_dma(BandArgs a)
         const uint32_t t0 = tile_start(i);
         if (t0 < u1 && (uint64_t)t0 + R > u0) {       // wavefront-uniform
 
-        BandStage<NW> &S = st[i % kStages];
-        const uint32_t rows_l = lds_addr(&S.rows[0]);
-        const uint32_t crow_l = lds_addr(&S.crow2[0]) + 16 * h;
-        const uint32_t rid_l = lds_addr(&S.rid[0]), par_l = lds_addr(&S.par[0]);
+            BandStage<NW> &S = st[si];
+            const uint32_t rows_l = lds_addr(&S.rows[0]);
+            const uint32_t crow_l = lds_addr(&S.crow2[0]) + 16 * h;
+            const uint32_t rid_l = lds_addr(&S.rid[0]), par_l = lds_addr(&S.par[0]);
 
-        const int own = list_bound(L, cq);
-        int th = own;
-        {
-            const int other = __shfl_xor(own, 32, 64);
-            th = other < th ? other : th;
-            th = ext < th ? ext : th;
-        }
-        const uint32_t rlo = lo > t0 ? std::min<uint32_t>(lo - t0, R) : 0u;
-        const uint32_t rhi = hi > t0 ? std::min<uint32_t>(hi - t0, R) : 0u;
-        if (!live || rlo >= rhi) th = INT32_MIN;
-        int hb = th >> 1;
-        int pend_h = 0;
-        uint32_t pend_r = kNoRow;
-        auto insert_pending = [&]() {
-            uint32_t p = lds_u8(par_l + pend_r), id = lds_b32(rid_l + 4 * pend_r);
-            asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(p), "+v"(id));
-            const int t = 2 * pend_h + (int)p;
-            const uint64_t key = ((uint64_t)(uint32_t)(t + cq) << 32) | id;
-            if (key < L[KR - 1]) {
-#pragma unroll
-                for (int m = KR - 1; m > 0; m--)
-                    L[m] = key < L[m - 1] ? L[m - 1] : (key < L[m] ? key : L[m]);
-                L[0] = key < L[0] ? key : L[0];
-                const int b = list_bound(L, cq);
-                th = b < th ? b : th;
-                hb = th >> 1;
+            const int own = list_bound(L, cq);
+            int th = own;
+            {
+                const int other = __shfl_xor(own, 32, 64);
+                th = other < th ? other : th;
+                th = ext < th ? ext : th;
             }
-            pend_r = kNoRow;
-        };
-        // this lane's A operand addresses and crow2 address in this stage
-        const uint32_t ab0 = rows_l + aoff[0], ab1 = rows_l + aoff[1], ab2 = rows_l + aoff[2],
-                       ab3 = rows_l + aoff[3];
-        // one 32-row block; RB is a compile-time constant, so that the block's
-        // LDS offsets are immediates
-        auto block32 = [&](auto rbc) {
-            constexpr uint32_t RB = decltype(rbc)::value;
-            v4i c0 = lds_b128<RB * 128>(crow_l), c1 = lds_b128<RB * 128 + 32>(crow_l),
-                c2 = lds_b128<RB * 128 + 64>(crow_l), c3 = lds_b128<RB * 128 + 96>(crow_l);
-            v4i a0 = lds_b128<RB * 4096>(ab0), a1 = lds_b128<RB * 4096>(ab1),
-                a2 = lds_b128<RB * 4096>(ab2), a3 = lds_b128<RB * 4096>(ab3);
-            asm volatile("s_waitcnt lgkmcnt(3)" : "+v"(c0), "+v"(c1), "+v"(c2), "+v"(c3), "+v"(a0));
-            v16i acc = v16i{c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w,
-                            c2.x, c2.y, c2.z, c2.w, c3.x, c3.y, c3.z, c3.w};
-            acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, bq[0], acc, 0, 0, 0);
-            __builtin_amdgcn_sched_barrier(0);     // each product starts as its operand lands
-            asm volatile("s_waitcnt lgkmcnt(2)" : "+v"(a1));
-            acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, bq[1], acc, 0, 0, 0);
-            __builtin_amdgcn_sched_barrier(0);
-            asm volatile("s_waitcnt lgkmcnt(1)" : "+v"(a2));
-            acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, bq[2], acc, 0, 0, 0);
-            __builtin_amdgcn_sched_barrier(0);
-            asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(a3));
-            acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a3, bq[3], acc, 0, 0, 0);
-            const int m0 = std::min(std::min(acc[0], acc[1]), acc[2]);
-            const int m1 = std::min(std::min(acc[3], acc[4]), acc[5]);
-            const int m2 = std::min(std::min(acc[6], acc[7]), acc[8]);
-            const int m3 = std::min(std::min(acc[9], acc[10]), acc[11]);
-            const int m4 = std::min(std::min(acc[12], acc[13]), acc[14]);
-            const int mm = std::min(std::min(std::min(m0, m1), m2),
-                                    std::min(std::min(m3, m4), acc[15]));
-            if (mm > hb) return;        // rare once the lists are full
-            int hm[4];
+            const uint32_t rlo = lo > t0 ? std::min<uint32_t>(lo - t0, R) : 0u;
+            const uint32_t rhi = hi > t0 ? std::min<uint32_t>(hi - t0, R) : 0u;
+            if (!live || rlo >= rhi) th = INT32_MIN;
+            int hb = th >> 1;
+            int pend_h = 0;
+            uint32_t pend_r = kNoRow;
+            auto insert_pending = [&]() {
+                uint32_t p = lds_u8(par_l + pend_r), id = lds_b32(rid_l + 4 * pend_r);
+                asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(p), "+v"(id));
+                const int t = 2 * pend_h + (int)p;
+                const uint64_t key = ((uint64_t)(uint32_t)(t + cq) << 32) | id;
+                if (key < L[KR - 1]) {
 #pragma unroll
-            for (int g = 0; g < 4; g++)
-                hm[g] = std::min(std::min(acc[4 * g], acc[4 * g + 1]),
-                                 std::min(acc[4 * g + 2], acc[4 * g + 3]));
+                    for (int m = KR - 1; m > 0; m--)
+                        L[m] = key < L[m - 1] ? L[m - 1] : (key < L[m] ? key : L[m]);
+                    L[0] = key < L[0] ? key : L[0];
+                    const int b = list_bound(L, cq);
+                    th = b < th ? b : th;
+                    hb = th >> 1;
+                }
+                pend_r = kNoRow;
+            };
+            // this lane's A operand addresses and crow2 address in this stage
+            const uint32_t ab0 = rows_l + aoff[0], ab1 = rows_l + aoff[1], ab2 = rows_l + aoff[2],
+                           ab3 = rows_l + aoff[3];
+            // one 32-row block; RB is a compile-time constant, so that the block's
+            // LDS offsets are immediates
+            auto block32 = [&](auto rbc) {
+                constexpr uint32_t RB = decltype(rbc)::value;
+                v4i c0 = lds_b128<RB * 128>(crow_l), c1 = lds_b128<RB * 128 + 32>(crow_l),
+                    c2 = lds_b128<RB * 128 + 64>(crow_l), c3 = lds_b128<RB * 128 + 96>(crow_l);
+                v4i a0 = lds_b128<RB * 4096>(ab0), a1 = lds_b128<RB * 4096>(ab1),
+                    a2 = lds_b128<RB * 4096>(ab2), a3 = lds_b128<RB * 4096>(ab3);
+                asm volatile("s_waitcnt lgkmcnt(3)" : "+v"(c0), "+v"(c1), "+v"(c2), "+v"(c3), "+v"(a0));
+                v16i acc = v16i{c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w,
+                                c2.x, c2.y, c2.z, c2.w, c3.x, c3.y, c3.z, c3.w};
+                acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, bq[0], acc, 0, 0, 0);
+                asm volatile("s_waitcnt lgkmcnt(2)" : "+v"(a1));
+                acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, bq[1], acc, 0, 0, 0);
+                asm volatile("s_waitcnt lgkmcnt(1)" : "+v"(a2));
+                acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, bq[2], acc, 0, 0, 0);
+                asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(a3));
+                acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a3, bq[3], acc, 0, 0, 0);
+                const int m0 = std::min(std::min(acc[0], acc[1]), acc[2]);
+                const int m1 = std::min(std::min(acc[3], acc[4]), acc[5]);
+                const int m2 = std::min(std::min(acc[6], acc[7]), acc[8]);
+                const int m3 = std::min(std::min(acc[9], acc[10]), acc[11]);
+                const int m4 = std::min(std::min(acc[12], acc[13]), acc[14]);
+                const int mm = std::min(std::min(std::min(m0, m1), m2),
+                                        std::min(std::min(m3, m4), acc[15]));
+                if (mm > hb) return;        // rare once the lists are full
+                int hm[4];
 #pragma unroll
-            for (int g = 0; g < 4; g++) {
-                const uint32_t r0 = RB * 32 + 8 * g + 4 * h;
-                if (hm[g] <= hb) {
+                for (int g = 0; g < 4; g++)
+                    hm[g] = std::min(std::min(acc[4 * g], acc[4 * g + 1]),
+                                     std::min(acc[4 * g + 2], acc[4 * g + 3]));
 #pragma unroll
-                    for (int j = 0; j < 4; j++) {
-                        if (acc[4 * g + j] <= hb && r0 + j - rlo < rhi - rlo) {
-                            if (pend_r != kNoRow) insert_pending();
-                            pend_h = acc[4 * g + j];
-                            pend_r = r0 + j;
+                for (int g = 0; g < 4; g++) {
+                    const uint32_t r0 = RB * 32 + 8 * g + 4 * h;
+                    if (hm[g] <= hb) {
+#pragma unroll
+                        for (int j = 0; j < 4; j++) {
+                            if (acc[4 * g + j] <= hb && r0 + j - rlo < rhi - rlo) {
+                                if (pend_r != kNoRow) insert_pending();
+                                pend_h = acc[4 * g + j];
+                                pend_r = r0 + j;
+                            }
                         }
                     }
                 }
+            };
+            block32(std::integral_constant<uint32_t, 0>{});
+            block32(std::integral_constant<uint32_t, 1>{});
+            if constexpr (R / 32 > 2) {
+                block32(std::integral_constant<uint32_t, 2>{});
+                block32(std::integral_constant<uint32_t, 3>{});
             }
-        };
-        block32(std::integral_constant<uint32_t, 0>{});
-        block32(std::integral_constant<uint32_t, 1>{});
-        if constexpr (R / 32 > 2) {
-            block32(std::integral_constant<uint32_t, 2>{});
-            block32(std::integral_constant<uint32_t, 3>{});
-        }
-        if (pend_r != kNoRow) insert_pending();
+            if (pend_r != kNoRow) insert_pending();
         }
         if (i + kStages - 1 < T) {
             // the bound copy goes before the tile's copies, hence the compiler
@@ -782,7 +785,7 @@ void k_band_dma(BandArgs a)
             // passed this tile's barrier
             if ((i & 7) == 7 && lane < kMQ) dma4(a.bound + q, &bslot[wv][0]);
             asm volatile("" ::: "memory");
-            issue(i + kStages - 1);
+            issue(i + kStages - 1, sn);
         }
     }
 
