@@ -962,7 +962,9 @@ hc_status band_search(const IndexView &v, const uint8_t *d_queries, uint32_t nq,
     hipLaunchKernelGGL(k_band_fill, dim3((uint32_t)std::min<uint64_t>(4096, (nq + 255) / 256)),
                        dim3(256), 0, st, a.bound, (uint64_t)nq, kEmpty);
     hipLaunchKernelGGL(k_band_place, dim3(nq), dim3(64), 0, st, a);
-    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(kScanThreads), 0, st, a.counts, nc);
+    // each curve's buckets count every query once: one block per curve
+    hipLaunchKernelGGL(k_scan_excl_seg, dim3(v.curves), dim3(kScanThreads), 0, st, a.counts,
+                       (uint64_t)L.nbuckets, nq);
     const uint64_t nt = (uint64_t)nq * v.curves;
     hipLaunchKernelGGL(k_band_scatter, dim3((uint32_t)((nt + 255) / 256)), dim3(256), 0, st, a);
     if (w_fixed < kBandWideW) launch_band<4>(v, k, nq, a, st);

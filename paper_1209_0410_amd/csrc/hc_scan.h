@@ -1,5 +1,5 @@
-// Single-block exclusive prefix sum, shared by the index build and the uneven
-// search (each translation unit gets its own copy of the kernel).
+// Block-level exclusive prefix sums, shared by the index build, the uneven
+// search and the banded search (each translation unit gets its own copy).
 #pragma once
 
 #include "hc_internal.h"
@@ -22,13 +22,14 @@ static __device__ inline uint32_t wave_excl_scan(uint32_t v, uint32_t *total)
     return x - v;
 }
 
-// In-place exclusive prefix sum of n values, one block of kScanThreads.
-static __global__ __launch_bounds__(kScanThreads) void k_scan_excl(uint32_t *a, uint64_t n)
+// In-place exclusive prefix sum of n values by one block of kScanThreads,
+// starting from carry0.
+static __device__ inline void block_scan_excl(uint32_t *a, uint64_t n, uint32_t carry0)
 {
     __shared__ uint32_t wsum[kScanThreads / 64];
     __shared__ uint32_t carry_s;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    if (tid == 0) carry_s = 0;
+    if (tid == 0) carry_s = carry0;
     __syncthreads();
     for (uint64_t base = 0; base < n; base += (uint64_t)kScanThreads * 4) {
         uint32_t v[4];
@@ -61,6 +62,21 @@ static __global__ __launch_bounds__(kScanThreads) void k_scan_excl(uint32_t *a, 
         if (tid == kScanThreads - 1) carry_s = run;
         __syncthreads();
     }
+}
+
+// In-place exclusive prefix sum of n values, one block of kScanThreads.
+static __global__ __launch_bounds__(kScanThreads) void k_scan_excl(uint32_t *a, uint64_t n)
+{
+    block_scan_excl(a, n, 0u);
+}
+
+// Segmented form, one block per segment: segment s (values [s len, (s + 1) len))
+// is scanned from s * seg_total.  Equal to the scan of all segments at once
+// when every segment sums to seg_total.
+static __global__ __launch_bounds__(kScanThreads) void k_scan_excl_seg(uint32_t *a, uint64_t len,
+                                                                       uint32_t seg_total)
+{
+    block_scan_excl(a + (uint64_t)blockIdx.x * len, len, blockIdx.x * seg_total);
 }
 
 }  // namespace hc
