@@ -529,6 +529,16 @@ __device__ inline uint32_t lds_u8(uint32_t addr)
     return r;
 }
 
+// f(integral_constant<uint32_t, i>) for i = 0 .. N - 1, in order
+template <int N, class F>
+__device__ inline void unroll_blocks(F &f)
+{
+    if constexpr (N > 0) {
+        unroll_blocks<N - 1>(f);
+        f(std::integral_constant<uint32_t, N - 1>{});
+    }
+}
+
 template <int KR, int NW>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(KR > 10 ? 3 : 4)))
 void k_band_dma(BandArgs a)
@@ -771,12 +781,7 @@ void k_band_dma(BandArgs a)
                     }
                 }
             };
-            block32(std::integral_constant<uint32_t, 0>{});
-            block32(std::integral_constant<uint32_t, 1>{});
-            if constexpr (R / 32 > 2) {
-                block32(std::integral_constant<uint32_t, 2>{});
-                block32(std::integral_constant<uint32_t, 3>{});
-            }
+            unroll_blocks<R / 32>(block32);
             if (pend_r != kNoRow) insert_pending();
         }
         if (i + kStages - 1 < T) {
