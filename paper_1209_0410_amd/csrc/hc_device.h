@@ -31,6 +31,31 @@ __device__ inline uint64_t wave_min_u64(uint64_t v)
 // Number of keys below the query key in each curve c < C, for the curves
 // c = first + j * step (j < CPW) handled by the calling wave.  Wave-uniform
 // control flow; cnt[j] is the position of curve first + j * step.
+// Every load is issued unconditionally from an address inside the table
+// (entry 0 of curve 0 standing in for slots that do not exist) and masked
+// afterwards, so that the loads of all curves at one level are in flight
+// together: a level costs one memory latency, not one per curve.
+// Ties the 8 loaded keys together: every load is issued before the first of
+// them is compared (the compiler would otherwise load, wait and compare one
+// curve at a time).
+template <int CPW>
+__device__ inline void keys_landed(Key (&kk)[CPW])
+{
+    if constexpr (CPW == 8) {
+        asm volatile(""
+                     : "+v"(kk[0].hi), "+v"(kk[0].lo), "+v"(kk[1].hi), "+v"(kk[1].lo),
+                       "+v"(kk[2].hi), "+v"(kk[2].lo), "+v"(kk[3].hi), "+v"(kk[3].lo),
+                       "+v"(kk[4].hi), "+v"(kk[4].lo), "+v"(kk[5].hi), "+v"(kk[5].lo),
+                       "+v"(kk[6].hi), "+v"(kk[6].lo), "+v"(kk[7].hi), "+v"(kk[7].lo));
+    }
+}
+
+// a < b on 128-bit keys without short-circuit control flow
+__device__ inline bool key_less_nb(const Key &a, const Key &b)
+{
+    return (a.hi < b.hi) | ((a.hi == b.hi) & (a.lo < b.lo));
+}
+
 template <int CPW>
 __device__ inline void locate(const IndexView &v, const Key *qk_row, uint32_t first,
                               uint32_t step, int lane, uint64_t (&cnt)[CPW])
@@ -38,22 +63,25 @@ __device__ inline void locate(const IndexView &v, const Key *qk_row, uint32_t fi
     const uint32_t C = v.curves;
     const uint32_t D = v.levels;
     Key qk[CPW];
+    bool on[CPW];
+    uint32_t cc[CPW];
 #pragma unroll
     for (int j = 0; j < CPW; j++) {
         const uint32_t c = first + j * step;
-        qk[j] = c < C ? qk_row[c] : Key{0, 0};
+        on[j] = c < C;
+        cc[j] = on[j] ? c : 0u;
+        qk[j] = qk_row[cc[j]];
     }
     {   // top table: at most 64 entries
         Key kk[CPW];
         const bool valid = (uint64_t)lane < v.len[D];
+        const uint32_t li = valid ? (uint32_t)lane : 0u;
+#pragma unroll
+        for (int j = 0; j < CPW; j++) kk[j] = v.lvl[cc[j]][D][li];
+        keys_landed(kk);
 #pragma unroll
         for (int j = 0; j < CPW; j++) {
-            const uint32_t c = first + j * step;
-            kk[j] = (c < C && valid) ? v.lvl[c][D][lane] : Key{~0ull, ~0ull};
-        }
-#pragma unroll
-        for (int j = 0; j < CPW; j++) {
-            const bool less = (first + j * step < C) && valid && key_less(kk[j], qk[j]);
+            const bool less = on[j] & valid & key_less_nb(kk[j], qk[j]);
             cnt[j] = (uint64_t)__popcll(__ballot(less));
         }
     }
@@ -63,19 +91,19 @@ __device__ inline void locate(const IndexView &v, const Key *qk_row, uint32_t fi
         // means every key is >= qkey.
         Key kk[CPW];
         uint64_t base[CPW];
+        bool ok[CPW];
         const uint64_t len = v.len[L - 1];
 #pragma unroll
         for (int j = 0; j < CPW; j++) {
-            const uint32_t c = first + j * step;
             base[j] = cnt[j] ? (cnt[j] - 1) * kFan : 0;
             const uint64_t idx = base[j] + lane;
-            kk[j] = (c < C && cnt[j] && idx < len) ? v.lvl[c][L - 1][idx] : Key{~0ull, ~0ull};
+            ok[j] = on[j] & (cnt[j] != 0) & (idx < len);
+            kk[j] = v.lvl[cc[j]][L - 1][ok[j] ? idx : 0];
         }
+        keys_landed(kk);
 #pragma unroll
         for (int j = 0; j < CPW; j++) {
-            const uint32_t c = first + j * step;
-            const uint64_t idx = base[j] + lane;
-            const bool less = c < C && cnt[j] && idx < len && key_less(kk[j], qk[j]);
+            const bool less = ok[j] & key_less_nb(kk[j], qk[j]);
             const uint64_t m = __ballot(less);
             cnt[j] = cnt[j] ? base[j] + (uint64_t)__popcll(m) : 0;
         }
