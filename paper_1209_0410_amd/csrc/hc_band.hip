@@ -448,19 +448,20 @@ void k_band(BandArgs a)
 // The same work and the same results as k_band, but a tile's rows, their
 // floor(crow / 2), crow mod 2 and list ids come from the row store by LDS DMA
 // (global_load_lds_dwordx4: lane l of one instruction writes its 16 bytes at
-// the instruction's LDS base + 16 l).  No registers hold a tile on its way,
-// so kStages tiles are in LDS at once: while tile i is worked on, tiles
-// i + 1 .. i + kStages - 2 are in flight, and tile i + kStages - 1 is issued
-// into the stage tile i - 1 used; one barrier per tile.  Tiles are aligned to
-// their size in the list (the row store is padded to a multiple of 256
-// entries), which keeps every 16-byte copy aligned and inside the store.
+// the instruction's LDS base + 16 l).  No registers hold a tile on its way.
+// Tiles go in groups of kTPB through two sets of stages: while group g is
+// worked on, group g + 1 is in flight into the stages group g - 1 used; one
+// wait and one barrier per group.  Tiles are aligned to their size in the
+// list (the row store is padded to a multiple of 256 entries), which keeps
+// every 16-byte copy aligned and inside the store.
 //
 // The compiler does not follow LDS DMA closely enough (it would wait for
 // every copy in flight before any LDS read), so the reads of staged data are
-// ds_read instructions with explicit lgkmcnt waits, and each wavefront counts
-// its own copies for the vmcnt waits.
+// ds_read instructions with explicit lgkmcnt waits, and the vmcnt waits are
+// explicit too.
 // ---------------------------------------------------------------------------
-constexpr int kStages = 3;
+constexpr int kTPB = 2;                 // tiles per barrier
+constexpr int kStages = 2 * kTPB;
 
 template <int NW>
 struct BandStage {
@@ -488,23 +489,6 @@ __device__ inline void dma16(const void *g, void *lds)
 __device__ inline void dma4(const void *g, void *lds)
 {
     __builtin_amdgcn_global_load_lds(g, (lds_void *)lds, 4, 0, 0);
-}
-
-// s_waitcnt vmcnt(n), n <= 9 (expcnt and lgkmcnt left alone)
-__device__ inline void wait_vm(uint32_t n)
-{
-    switch (n) {
-    case 0: __builtin_amdgcn_s_waitcnt(0x0F70); break;
-    case 1: __builtin_amdgcn_s_waitcnt(0x0F71); break;
-    case 2: __builtin_amdgcn_s_waitcnt(0x0F72); break;
-    case 3: __builtin_amdgcn_s_waitcnt(0x0F73); break;
-    case 4: __builtin_amdgcn_s_waitcnt(0x0F74); break;
-    case 5: __builtin_amdgcn_s_waitcnt(0x0F75); break;
-    case 6: __builtin_amdgcn_s_waitcnt(0x0F76); break;
-    case 7: __builtin_amdgcn_s_waitcnt(0x0F77); break;
-    case 8: __builtin_amdgcn_s_waitcnt(0x0F78); break;
-    default: __builtin_amdgcn_s_waitcnt(0x0F79); break;
-    }
 }
 
 template <int OFF>
@@ -646,9 +630,8 @@ void k_band_dma(BandArgs a)
     const int *crow2_c = a.v.crow2[c];
     const uint32_t *rid_c = a.v.rid[c];
     const uint8_t *par_c = a.v.par[c];
-    // copies per tile issued by this wavefront: two 1 KiB parts of the rows,
-    // and for wavefronts 0, 1, 2 the crow2, id and parity parts
-    const uint32_t gbase = wv < 3 ? 3u : 2u;
+    // a tile's copies: each wavefront two 1 KiB parts of the rows, and
+    // wavefronts 0, 1, 2 the crow2, id and parity parts
     auto issue = [&](uint32_t j, uint32_t sj) {
         BandStage<NW> &S = st[sj];
         const uint64_t e0 = tile_start(j);
@@ -674,30 +657,11 @@ void k_band_dma(BandArgs a)
     for (int s4 = 0; s4 < 4; s4++)
         aoff[s4] = (uint32_t)qn * 128 + ((uint32_t)(2 * s4 + h) ^ (((uint32_t)qn >> 1) & 7)) * 16;
 
-    // Tile i sits in stage i % kStages.  Its copies are complete once at most
-    // the copies of the tiles after it that are in flight (up to kStages - 2
-    // tiles, gbase instructions each) are outstanding; a bound copy, issued
-    // before a tile's copies, only makes that wait longer.  The bound copied
-    // at tile m (m % 8 == 7) is complete at tile m + kStages - 2.
-    static_assert(kStages >= 3 && 3 * (kStages - 2) <= 9, "wait counts");
-    for (uint32_t j = 0; j + 1 < kStages && j < T; j++) issue(j, j);
-    uint32_t si = 0, sn = kStages - 1;       // stages of tile i and of tile i + kStages - 1
-    for (uint32_t i = 0; i < T; i++, si = si + 1 == kStages ? 0 : si + 1,
-                  sn = sn + 1 == kStages ? 0 : sn + 1) {
-        const uint32_t later = std::min<uint32_t>(kStages - 2, T - 1 - i);
-        wait_vm(gbase * later);
-        __builtin_amdgcn_s_barrier();
-        if (i >= 7 + kStages - 2 && ((i - (kStages - 2)) & 7) == 7 && i + 1 < T) {
-            uint32_t b = lds_b32(lds_addr(&bslot[wv][qn]));
-            asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(b));
-            if (live && b != kEmpty) {
-                const int e = (int)b - cq;
-                ext = e < ext ? e : ext;
-            }
-        }
+    // tile i of the union, from stage si
+    auto do_tile = [&](uint32_t i, uint32_t si) {
         const uint32_t t0 = tile_start(i);
-        if (t0 < u1 && (uint64_t)t0 + R > u0) {       // wavefront-uniform
-
+        if (!(t0 < u1 && (uint64_t)t0 + R > u0)) return;       // wavefront-uniform
+        {
             BandStage<NW> &S = st[si];
             const uint32_t rows_l = lds_addr(&S.rows[0]);
             const uint32_t crow_l = lds_addr(&S.crow2[0]) + 16 * h;
@@ -784,13 +748,42 @@ void k_band_dma(BandArgs a)
             unroll_blocks<R / 32>(block32);
             if (pend_r != kNoRow) insert_pending();
         }
-        if (i + kStages - 1 < T) {
-            // the bound copy goes before the tile's copies, hence the compiler
-            // barrier; stage (i - 1) % kStages is free, every wavefront having
-            // passed this tile's barrier
-            if ((i & 7) == 7 && lane < kMQ) dma4(a.bound + q, &bslot[wv][0]);
+    };
+
+    // Groups of kTPB tiles in ping-pong stages: group g sits in stages
+    // (g & 1) * kTPB + j.  Group g + 1 is issued right after group g's
+    // barrier, into the stages group g - 1 used, so one wait (everything
+    // issued so far) and one barrier serve kTPB tiles.  The bound copied
+    // with group g + 1 (every 4 groups) is read with it.
+    const uint32_t NG = (T + kTPB - 1) / kTPB;
+    auto issue_group = [&](uint32_t g) {
+#pragma unroll
+        for (int j = 0; j < kTPB; j++) {
+            const uint32_t t = g * kTPB + j;
+            if (t < T) issue(t, (g & 1) * kTPB + j);
+        }
+    };
+    if (NG > 0) issue_group(0);
+    for (uint32_t g = 0; g < NG; g++) {
+        __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0)
+        __builtin_amdgcn_s_barrier();
+        if (g >= 1 && ((g - 1) & 3) == 3) {
+            uint32_t b = lds_b32(lds_addr(&bslot[wv][qn]));
+            asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(b));
+            if (live && b != kEmpty) {
+                const int e = (int)b - cq;
+                ext = e < ext ? e : ext;
+            }
+        }
+        if (g + 1 < NG) {
+            if ((g & 3) == 3 && lane < kMQ) dma4(a.bound + q, &bslot[wv][0]);
             asm volatile("" ::: "memory");
-            issue(i + kStages - 1, sn);
+            issue_group(g + 1);
+        }
+#pragma unroll
+        for (int j = 0; j < kTPB; j++) {
+            const uint32_t t = g * kTPB + j;
+            if (t < T) do_tile(t, (g & 1) * kTPB + j);
         }
     }
 
