@@ -111,6 +111,30 @@ def test_insert_twice_then_search(oracle, data):
         assert (u32(ids) == rid).all() and (u32(d) == rd).all(), (k, w)
 
 
+def test_zorder_rowstore_and_inserted_rowstore(oracle, data):
+    """The row store (tiles copied into LDS) on a Z-order index and on an index
+    made by insertion: banded searches stay bit-exact."""
+    import torch
+    from paper_1209_0410_amd.index import Index
+    db, q = data
+    gq = torch.from_numpy(q).cuda()
+    g = torch.from_numpy(db).cuda()
+    zix = Index(g, curve="zorder")
+    zix.attach_rowstore()
+    zo = oracle.Index(db, oracle.Params(curve="zorder"))
+    for k, w in [(10, 600), (4, 9000)]:
+        ids, d = zix.search(gq, k, w, path=2)
+        rid, rd = zo.search(q, k, w)
+        assert (u32(ids) == rid).all() and (u32(d) == rd).all(), ("zorder", k, w)
+    ins = Index(g[:70_000]).insert(g)
+    ins.attach_rowstore()
+    ho = oracle.Index(db)
+    for k, w in [(10, 600), (16, 9000)]:
+        ids, d = ins.search(gq, k, w, path=2)
+        rid, rd = ho.search(q, k, w)
+        assert (u32(ids) == rid).all() and (u32(d) == rd).all(), ("inserted", k, w)
+
+
 def test_insert_zorder(oracle, data):
     import torch
     from paper_1209_0410_amd.index import Index
