@@ -70,21 +70,38 @@ class HbmBudget:
 
 
 class _Slot:
+    """One stream's buffers.  A batch of nq requests travels in one copy each
+    way: in, the rows, k and the model's k' packed as [nq x 128 | nq | nq]
+    (136 B per request); out, the ids then the distances, nq x k_stride each."""
+    IN_BYTES = 136
+
     def __init__(self, ix, cap, k_stride, dev, cfg):
         self.stream = torch.cuda.Stream(device=dev)
-        self.q = torch.empty((cap, 128), dtype=torch.uint8, device=dev)
-        self.k = torch.empty(cap, dtype=torch.int32, device=dev)
-        self.kf = torch.empty(cap, dtype=torch.int32, device=dev)
+        self.k_stride = k_stride
+        self.d_in = torch.empty(cap * self.IN_BYTES, dtype=torch.uint8, device=dev)
+        self.h_in = torch.empty(cap * self.IN_BYTES, dtype=torch.uint8).pin_memory()
         self.w = torch.empty(cap, dtype=torch.int32, device=dev)
         self.feat = torch.empty((cap, learned.FEATURES), dtype=torch.float32, device=dev)
-        self.ids = torch.empty((cap, k_stride), dtype=torch.int32, device=dev)
-        self.dists = torch.empty((cap, k_stride), dtype=torch.int32, device=dev)
+        self.d_out = torch.empty(2 * cap * k_stride, dtype=torch.int32, device=dev)
+        self.h_out = torch.empty(2 * cap * k_stride, dtype=torch.int32).pin_memory()
         self.scratch = ix.uneven_scratch(cap, k_stride, cfg)
         self.fscratch = ix.new_scratch(cap)
-        self.host_ids = torch.empty((cap, k_stride), dtype=torch.int32).pin_memory()
-        self.host_dists = torch.empty((cap, k_stride), dtype=torch.int32).pin_memory()
         self.done = torch.cuda.Event()
         self.busy = False
+
+    def inputs(self, nq):
+        """Device views (rows, k, k') of a batch of nq in d_in."""
+        b = self.d_in[:nq * self.IN_BYTES]
+        q = b[:nq * 128].view(nq, 128)
+        k = b[nq * 128:nq * 132].view(torch.int32)
+        kf = b[nq * 132:nq * 136].view(torch.int32)
+        return q, k, kf
+
+    def outputs(self, nq, host=False):
+        """(ids, dists) of a batch of nq, each nq x k_stride, in d_out or h_out."""
+        b = (self.h_out if host else self.d_out)[:2 * nq * self.k_stride]
+        m = nq * self.k_stride
+        return b[:m].view(nq, self.k_stride), b[m:].view(nq, self.k_stride)
 
 
 def batch_bytes(nq, k_stride, curves=8, max_split=32):
@@ -119,14 +136,19 @@ class Server:
 
     def _launch(self, slot, hq, hk, hkf, lo, hi):
         nq = hi - lo
+        # pack the batch on the host (rows, k, k'), then one copy in
+        hin = slot.h_in[:nq * _Slot.IN_BYTES].numpy()
+        hin[:nq * 128] = hq[lo:hi].reshape(-1)
+        hin[nq * 128:nq * 132] = hk[lo:hi].view(np.uint8)
+        hin[nq * 132:nq * 136] = hkf[lo:hi].view(np.uint8)
         with torch.cuda.stream(slot.stream):
-            slot.q[:nq].copy_(hq[lo:hi], non_blocking=True)
-            slot.k[:nq].copy_(hk[lo:hi], non_blocking=True)
-            slot.kf[:nq].copy_(hkf[lo:hi], non_blocking=True)
-            q = slot.q[:nq]
+            slot.d_in[:nq * _Slot.IN_BYTES].copy_(slot.h_in[:nq * _Slot.IN_BYTES],
+                                                   non_blocking=True)
+            q, k, kf = slot.inputs(nq)
+            ids, dists = slot.outputs(nq)
             if self.model is not None:
                 kmax = int(self.k_stride)
-                capi.call("hc_features", self.ix.handle, ctp(q), nq, kmax, ctp(slot.kf),
+                capi.call("hc_features", self.ix.handle, ctp(q), nq, kmax, ctp(kf),
                           ctp(slot.feat), ctp(slot.fscratch), slot.fscratch.numel(),
                           stream_of(slot.stream))
                 capi.call("hc_mlp_infer", ctp(self.model.bf16), ctp(self.model.norm),
@@ -137,11 +159,11 @@ class Server:
             else:
                 wp = None
             capi.call("hc_search_uneven", self.ix.handle, ctp(q), nq, self.w_fixed,
-                      ctp(wp) if wp is not None else None, 1, ctp(slot.k), self.k_stride,
-                      ctp(slot.ids), ctp(slot.dists), ctp(slot.scratch), slot.scratch.numel(),
+                      ctp(wp) if wp is not None else None, 1, ctp(k), self.k_stride,
+                      ctp(ids), ctp(dists), ctp(slot.scratch), slot.scratch.numel(),
                       _cfgp(self.cfg), stream_of(slot.stream))
-            slot.host_ids[:nq].copy_(slot.ids[:nq], non_blocking=True)
-            slot.host_dists[:nq].copy_(slot.dists[:nq], non_blocking=True)
+            m = 2 * nq * self.k_stride
+            slot.h_out[:m].copy_(slot.d_out[:m], non_blocking=True)
             slot.done.record(slot.stream)
         slot.busy = True
 
@@ -149,11 +171,10 @@ class Server:
         """Serves requests i (arrival time arrivals[i] s, row queries[i], k ks[i]).
         Returns per-request latency (s) and, if asked, the results."""
         R = len(arrivals)
-        hq = torch.from_numpy(queries).pin_memory()
-        hk = torch.from_numpy(np.ascontiguousarray(ks, np.uint32).view(np.int32)).pin_memory()
+        hq = np.ascontiguousarray(queries, np.uint8)
+        hk = np.ascontiguousarray(ks, np.uint32)
         # the model sees k' = min(k, k_feature): the depth it was trained for
-        hkf = torch.from_numpy(np.minimum(np.asarray(ks, np.uint32), self.k_feature)
-                               .astype(np.uint32).view(np.int32)).pin_memory()
+        hkf = np.minimum(hk, self.k_feature).astype(np.uint32)
         done_at = np.zeros(R)
         res_ids = np.zeros((R, self.k_stride), np.uint32) if keep_results else None
         res_d = np.zeros((R, self.k_stride), np.uint32) if keep_results else None
@@ -200,8 +221,9 @@ class Server:
                 t_done = clock() if realtime else 0.0
                 done_at[lo:hi] = t_done
                 if keep_results:
-                    res_ids[lo:hi] = slot.host_ids[:hi - lo].numpy().view(np.uint32)
-                    res_d[lo:hi] = slot.host_dists[:hi - lo].numpy().view(np.uint32)
+                    hids, hd = slot.outputs(hi - lo, host=True)
+                    res_ids[lo:hi] = hids.numpy().view(np.uint32)
+                    res_d[lo:hi] = hd.numpy().view(np.uint32)
                 slot.busy = False
                 self.budget.give(nb)
             if log is not None and realtime and now >= next_log:
