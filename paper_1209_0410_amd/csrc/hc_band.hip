@@ -7,8 +7,10 @@
 //  1. every query's place in every curve (the same descent as the search);
 //  2. per curve, the queries ordered by place (a counting sort on place
 //     buckets of 2^kBucketShift entries);
-//  3. a block takes 256 consecutive queries of one curve and streams the
-//     union of their windows through LDS, 128 list entries at a time; the
+//  3. a block takes 256 consecutive queries of one curve (128 below
+//     kBandWideW) and streams the union of their windows through LDS, 128
+//     (64) list entries at a time: gathered by id and transformed on the way
+//     (k_band), or copied from the row store by LDS DMA (k_band_dma); the
 //     distances of 32 queries against the tile's rows come from the matrix
 //     cores (below), and every entry inside a query's own window is offered,
 //     as (distance, id), to that query's register top-k;
