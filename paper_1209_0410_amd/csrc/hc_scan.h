@@ -70,6 +70,44 @@ static __global__ __launch_bounds__(kScanThreads) void k_scan_excl(uint32_t *a, 
     block_scan_excl(a, n, 0u);
 }
 
+// Multi-block form for long arrays: kScanTile values per block.
+//  k_scan_tile_sums: sums[b] = the sum of tile b;
+//  k_scan_excl over the sums (one block);
+//  k_scan_tiles: tile b scanned in place from sums[b].
+constexpr uint64_t kScanTile = (uint64_t)kScanThreads * 4;
+
+static __global__ __launch_bounds__(kScanThreads) void k_scan_tile_sums(const uint32_t *a,
+                                                                        uint64_t n,
+                                                                        uint32_t *sums)
+{
+    __shared__ uint32_t wsum[kScanThreads / 64];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const uint64_t i = base + (uint64_t)tid * 4 + j;
+        s += i < n ? a[i] : 0u;
+    }
+    uint32_t wt;
+    wave_excl_scan(s, &wt);
+    if (lane == 0) wsum[wave] = wt;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t t = 0;
+        for (int i = 0; i < kScanThreads / 64; i++) t += wsum[i];
+        sums[blockIdx.x] = t;
+    }
+}
+
+static __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(uint32_t *a, uint64_t n,
+                                                                    const uint32_t *sums)
+{
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    const uint64_t len = n - base < kScanTile ? n - base : kScanTile;
+    block_scan_excl(a + base, len, sums[blockIdx.x]);
+}
+
 // Segmented form, one block per segment: segment s (values [s len, (s + 1) len))
 // is scanned from s * seg_total.  Equal to the scan of all segments at once
 // when every segment sums to seg_total.

@@ -13,7 +13,7 @@
 // Launch sequence (one stream):
 //   k_encode_rows   query keys
 //   k_plan          positions, number of items per query, queue reset
-//   k_scan_excl     item offsets per query (base[q]; base[nq] = item count)
+//   k_scan_*        item offsets per query (base[q]; base[nq] = item count)
 //   k_items         the persistent work loop
 //   k_merge         queries with more than one item
 #include <string.h>
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(64) void k_merge(UnevenArgs a)
 }
 
 struct UnevenLayout {
-    size_t qkeys, pos, base, queue, partial, total;
+    size_t qkeys, pos, base, sums, queue, partial, total;
 };
 
 static UnevenLayout uneven_layout(uint32_t curves, uint32_t nq, uint32_t k_stride,
@@ -237,6 +237,8 @@ static UnevenLayout uneven_layout(uint32_t curves, uint32_t nq, uint32_t k_strid
     off = align256(off + sizeof(uint32_t) * (size_t)nq * curves);
     L.base = off;
     off = align256(off + sizeof(uint32_t) * ((size_t)nq + 1));
+    L.sums = off;      // tile sums of the scan of base
+    off = align256(off + sizeof(uint32_t) * (((size_t)nq + 1 + kScanTile - 1) / kScanTile));
     L.queue = off;
     off = align256(off + sizeof(uint32_t));
     L.partial = off;
@@ -340,8 +342,17 @@ hc_status hc_search_uneven(const hc_index *idx, const uint8_t *d_queries, uint32
     hc_status rc = encode_rows(a.v, d_queries, nq, (Key *)(s + L.qkeys), st);
     if (rc != HC_OK) return rc;
     hipLaunchKernelGGL(k_plan, dim3(nq), dim3(64), 0, st, a);
-    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(kScanThreads), 0, st, a.base,
-                       (uint64_t)nq + 1);
+    {   // item offsets: one block per 4,096 queries, then the tile sums
+        const uint64_t nb1 = (uint64_t)nq + 1;
+        const uint32_t tiles = (uint32_t)((nb1 + kScanTile - 1) / kScanTile);
+        uint32_t *sums = (uint32_t *)(s + L.sums);
+        hipLaunchKernelGGL(k_scan_tile_sums, dim3(tiles), dim3(kScanThreads), 0, st, a.base, nb1,
+                           sums);
+        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(kScanThreads), 0, st, sums,
+                           (uint64_t)tiles);
+        hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(kScanThreads), 0, st, a.base, nb1,
+                           (const uint32_t *)sums);
+    }
     const bool big = k_stride > 16;
     const uint32_t blocks = big ? persistent_blocks<true>(per_cu) : persistent_blocks<false>(per_cu);
     if (blocks == 0) return HC_ERR_HIP;
