@@ -812,24 +812,46 @@ void k_band_dma(BandArgs a)
 }
 
 // One wavefront per query: the curves' lists, repeats dropped, k nearest.
-__global__ __launch_bounds__(64) void k_band_merge(BandArgs a)
+// Each curve's list is ascending with distinct ids, so the result is a merge
+// of their heads: the wavefront copies the C lists into LDS (one coalesced
+// load), then lane c < C follows the head of list c; per output the smallest
+// head is taken and every lane holding that key advances (a repeated id has
+// the same key in every curve, so it is taken once).
+constexpr int kMergeWaves = 4;
+__global__ __launch_bounds__(64 * kMergeWaves) void k_band_merge(BandArgs a)
 {
-    const int lane = threadIdx.x;
-    const uint32_t q = blockIdx.x;
-    const uint32_t C = a.v.curves;
-    const uint64_t nkeys = (uint64_t)C * a.k;
-    const uint64_t *src = a.partial + (uint64_t)q * C * a.k;
-    WaveTopK<kBandK> top;
-    top.init(a.k, nullptr, lane);
-    for (uint64_t s = 0; s < nkeys; s += 64) {
-        const uint64_t i = s + lane;
-        top.push(i < nkeys ? src[i] : kNone, lane);
+    __shared__ uint64_t lists[kMergeWaves][kMaxCurves * kBandK];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t q = blockIdx.x * kMergeWaves + wv;
+    if (q >= a.nq) return;                 // the whole wavefront; no barrier follows
+    const uint32_t C = a.v.curves, k = a.k;
+    const uint32_t nkeys = C * k;
+    const uint64_t *src = a.partial + (uint64_t)q * nkeys;
+    uint64_t *ls = lists[wv];
+    for (uint32_t i = lane; i < nkeys; i += 64) ls[i] = src[i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const bool mine = (uint32_t)lane < C;
+    uint32_t hc = 0;
+    uint64_t head = mine ? ls[lane * k] : kNone;
+    const uint64_t o = (uint64_t)q * k;
+    for (uint32_t j = 0; j < k; j++) {
+        uint64_t m = head;                 // minimum over lanes 0..7 (C <= 8)
+#pragma unroll
+        for (int x = 1; x < kMaxCurves; x <<= 1) {
+            const uint64_t y = shfl_xor_u64(m, x);
+            m = y < m ? y : m;
+        }
+        if (lane == 0) {
+            a.out_ids[o + j] = (uint32_t)m;
+            a.out_dists[o + j] = (uint32_t)(m >> 32);
+        }
+        if (mine && head == m && m != kNone) {
+            hc++;
+            head = hc < k ? ls[lane * k + hc] : kNone;
+        }
     }
-    const uint64_t o = (uint64_t)q * a.k;
-    top.finish(lane, [&](uint32_t j, uint64_t key) {
-        a.out_ids[o + j] = (uint32_t)key;
-        a.out_dists[o + j] = (uint32_t)(key >> 32);
-    });
 }
 
 // Row store of curve c: 8 lanes per list entry, each 16 bytes of the row
@@ -969,7 +991,8 @@ hc_status band_search(const IndexView &v, const uint8_t *d_queries, uint32_t nq,
     hipLaunchKernelGGL(k_band_scatter, dim3((uint32_t)((nt + 255) / 256)), dim3(256), 0, st, a);
     if (w_fixed < kBandWideW) launch_band<4>(v, k, nq, a, st);
     else launch_band<8>(v, k, nq, a, st);
-    hipLaunchKernelGGL(k_band_merge, dim3(nq), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(k_band_merge, dim3((nq + kMergeWaves - 1) / kMergeWaves),
+                       dim3(64 * kMergeWaves), 0, st, a);
     return last_hip();
 }
 
