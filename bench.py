@@ -67,6 +67,8 @@ def parse():
                     help="use this fixed w instead of calibrating it (profiling runs)")
     ap.add_argument("--uneven", type=int, default=200_000,
                     help="queries of the uneven batch (per-query w and k); 0 = skip")
+    ap.add_argument("--path", default="auto", choices=["auto", "gather", "band"],
+                    help="search path of the fixed-w legs (auto: the library's choice)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also copy 1 GiB device-to-device 3 times (counter calibration)")
     return ap.parse_args()
@@ -136,12 +138,17 @@ def main():
         kern = [e[1].elapsed_time(e[2]) for e in marks]
         return float(np.median(step)), float(np.mean(kern)), wall * 1e3
 
+    forced = {"auto": 0, "gather": 1, "band": 2}[a.path]
+
+    def path_of(w):
+        return path_name(forced if forced else ix.path(a.nq, k, w, sc.numel()))
+
     def fixed_step(w):
         def fn(ev=None, st=None):
             if ev: ev[0].record(st)
             ix.encode_queries(gq, sc)
             if ev: ev[1].record(st)
-            ix.search_encoded(gq, k, w, out, sc)
+            ix.search_encoded(gq, k, w, out, sc, path=forced)
             if ev: ev[2].record(st)
         return fn
 
@@ -172,7 +179,7 @@ def main():
         slots = window_slots(w)
         ab = alg_bytes(slots, uni)
         rows.append(dict(w=w, step_ms=step_ms, kernel_ms=kern_ms, qps=a.nq / step_ms * 1e3,
-                         path=path_name(ix.path(a.nq, k, w, sc.numel())),
+                         path=path_of(w),
                          recall=rec, union_per_query=uni / a.nq, alg_bytes=ab,
                          alg_GBs=ab / (kern_ms * 1e-3) / 1e9,
                          frac=ab / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS))
@@ -197,7 +204,7 @@ def main():
     f_ab = alg_bytes(window_slots(w_fix), f_uni)
     fixed = dict(w=w_fix, step_ms=fs, kernel_ms=fk, wall_ms=fwall, qps=a.nq / fs * 1e3,
                  recall=f_rec, union_per_query=f_uni / a.nq, alg_bytes=f_ab,
-                 alg_GBs=f_ab / (fk * 1e-3) / 1e9, path=path_name(ix.path(a.nq, k, w_fix, sc.numel())),
+                 alg_GBs=f_ab / (fk * 1e-3) / 1e9, path=path_of(w_fix),
                  alg_TOPs=2 * 128 * f_uni / (fk * 1e-3) / 1e12)
     log(f"fixed w={w_fix}: {fs:.3f} ms/step, {fixed['qps']:.3e} q/s, recall {f_rec:.4f}")
 
