@@ -69,6 +69,22 @@ def test_uneven_multi_item_queries(env, chunk, split):
     check_rows(sub, ids, d, w, k, 64)
 
 
+def test_uneven_batch_over_several_scan_tiles(env):
+    """9,000 queries: the item offsets are scanned one block per 4,096 queries
+    (three tiles, the last one ragged) and the tile sums are scanned after."""
+    import torch
+    from paper_1209_0410_amd import datagen
+    nq = 9000
+    q = datagen.make_queries(nq, seed=21)
+    rng = np.random.default_rng(21)
+    w = np.exp(rng.uniform(np.log(8), np.log(64), size=nq)).astype(np.uint32)
+    w[4095:4098] = [0, 1, 300]                    # around the first tile edge
+    k = rng.choice([1, 10, 100], size=nq).astype(np.uint32)
+    ids, d = env["gix"].search_uneven(torch.from_numpy(q).cuda(), w_per_query=as_gpu(w),
+                                      k_per_query=as_gpu(k), k_stride=100)
+    check_rows(dict(env, q=q), ids, d, w, k, 100)
+
+
 def test_uneven_fixed_w_and_k_matches_plain_search(env):
     gix, gq = env["gix"], env["gq"]
     a_ids, a_d = gix.search(gq, 10, 64)
