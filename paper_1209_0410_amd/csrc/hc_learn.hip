@@ -359,6 +359,64 @@ __global__ __launch_bounds__(256) void k_mlp_infer(MlpArgs a)
     }
 }
 
+// Inference for small batches: one wavefront per sample, lane j computing
+// hidden unit j of each layer with the terms in the same order as forward(),
+// so the outputs are bit-identical to k_mlp_infer's.
+constexpr int kInferWaves = 4;
+static_assert(kH1 == 64 && kH2 == 64, "one lane per hidden unit");
+__global__ __launch_bounds__(64 * kInferWaves) void k_mlp_infer_wave(MlpArgs a)
+{
+    __shared__ float w[kNP];
+    __shared__ float hs[kInferWaves][kH1 + kH2];
+    stage_params(a.params, w);      // block barrier: before any wavefront leaves
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t b = blockIdx.x * kInferWaves + wv;
+    if (b >= a.batch) return;
+    const uint32_t row = a.idx ? a.idx[b] : b;
+    float x[kIn];
+    load_x(a, row, x);
+    bool finite = true;
+#pragma unroll
+    for (int i = 0; i < kIn; i++) finite = finite && isfinite(x[i]);
+    float *h = hs[wv];
+    {
+        float s = w[oB1 + lane];
+#pragma unroll
+        for (int i = 0; i < kIn; i++) s = fmaf(w[oW1 + lane * kIn + i], x[i], s);
+        h[lane] = s > 0.0f ? s : 0.0f;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    {
+        float s = w[oB2 + lane];
+#pragma unroll 8
+        for (int i = 0; i < kH1; i++) s = fmaf(w[oW2 + lane * kH1 + i], h[i], s);
+        h[kH1 + lane] = s > 0.0f ? s : 0.0f;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float y = w[oB3];
+#pragma unroll 8
+    for (int o = 0; o < kH2; o++) y = fmaf(w[oW3 + o], h[kH1 + o], y);
+    if (lane != 0) return;
+    if (a.y_out) a.y_out[b] = finite ? y : NAN;
+    if (a.w_out) {
+        const float t = y + a.delta;
+        uint32_t out;
+        if (!finite || !isfinite(t)) {
+            out = a.w_fallback;
+        } else {
+            const float e = exp2f(t);
+            if (e >= (float)a.w_max) out = a.w_max;
+            else if (e <= (float)a.w_min) out = a.w_min;
+            else out = std::min<uint32_t>(std::max<uint32_t>((uint32_t)ceilf(e), a.w_min), a.w_max);
+        }
+        a.w_out[b] = out;
+    }
+}
+
 // Forward and backward of one sample; the record feeds k_mlp_grad.
 // loss = mean over the batch of (y - target)^2.
 __global__ __launch_bounds__(256) void k_mlp_sample(MlpArgs a)
@@ -562,7 +620,14 @@ hc_status hc_mlp_infer(const uint16_t *d_params_bf16, const float *d_norm, const
     a.w_fallback = w_fallback;
     a.w_out = d_w_out;
     a.y_out = d_y_out;
-    hipLaunchKernelGGL(k_mlp_infer, dim3((nq + 255) / 256), dim3(256), 0, (hipStream_t)stream, a);
+    // small batches (the serving loop's): a wavefront per sample; large ones:
+    // a thread per sample
+    if (nq <= 2048)
+        hipLaunchKernelGGL(k_mlp_infer_wave, dim3((nq + kInferWaves - 1) / kInferWaves),
+                           dim3(64 * kInferWaves), 0, (hipStream_t)stream, a);
+    else
+        hipLaunchKernelGGL(k_mlp_infer, dim3((nq + 255) / 256), dim3(256), 0,
+                           (hipStream_t)stream, a);
     return last_hip();
 }
 

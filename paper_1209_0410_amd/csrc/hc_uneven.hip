@@ -354,8 +354,10 @@ hc_status hc_search_uneven(const hc_index *idx, const uint8_t *d_queries, uint32
                            (const uint32_t *)sums);
     }
     const bool big = k_stride > 16;
-    const uint32_t blocks = big ? persistent_blocks<true>(per_cu) : persistent_blocks<false>(per_cu);
+    uint32_t blocks = big ? persistent_blocks<true>(per_cu) : persistent_blocks<false>(per_cu);
     if (blocks == 0) return HC_ERR_HIP;
+    // a query has at most max_split items: a small batch needs no full grid
+    blocks = (uint32_t)std::min<uint64_t>(blocks, (uint64_t)nq * max_split);
     if (big) {
         hipLaunchKernelGGL(k_items<true>, dim3(blocks), dim3(64), 0, st, a);
         hipLaunchKernelGGL(k_merge<true>, dim3(nq), dim3(64), 0, st, a);
