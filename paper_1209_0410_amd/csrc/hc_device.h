@@ -202,14 +202,33 @@ struct WaveTopK {
         }
     }
 
+    // Number of entries of the ascending array a[0, n) below x (LDS).
+    static __device__ uint32_t below(const uint64_t *a, uint32_t n, uint64_t x)
+    {
+        uint32_t lo = 0, hi = n;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (a[mid] < x) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo;
+    }
+
+    // Wave-collective (the block is this one wavefront).  The buffer is sorted
+    // (bitonic, over the next power of two above its fill), its repeats and the
+    // keys already in the running list are dropped, and the two ascending lists
+    // are merged by rank: a key's place in the result is its index plus the
+    // number of keys of the other list below it.
     __device__ void flush(int lane)
     {
+        uint32_t sz = 2;
+        while (sz < nbuf) sz <<= 1;
         __syncthreads();
-        for (uint32_t i = nbuf + lane; i < (uint32_t)kBuf; i += 64) sh->buf[i] = kNone;
+        for (uint32_t i = nbuf + lane; i < sz; i += 64) sh->buf[i] = kNone;
         __syncthreads();
-        for (uint32_t size = 2; size <= (uint32_t)kBuf; size <<= 1) {
+        for (uint32_t size = 2; size <= sz; size <<= 1) {
             for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-                for (uint32_t i = lane; i < (uint32_t)kBuf / 2; i += 64) {
+                for (uint32_t i = lane; i < sz / 2; i += 64) {
                     const uint32_t lo = 2 * stride * (i / stride) + (i % stride);
                     const uint32_t hi = lo + stride;
                     const bool up = (lo & size) == 0;
@@ -222,10 +241,41 @@ struct WaveTopK {
                 __syncthreads();
             }
         }
-        if (lane == 0) {
-            merge_distinct(sh->run, k, sh->buf, nbuf, k, sh->out);
-            for (uint32_t i = 0; i < k; i++) sh->run[i] = sh->out[i];
+        // valid entries of the running list (ascending, distinct, kNone after)
+        const uint32_t nr = below(sh->run, k, kNone);
+        // compact the buffer in place to its distinct keys not in the list; a
+        // round reads all of its 64 entries before any is written, and carries
+        // its last original entry to the next round
+        uint32_t nb2 = 0;
+        uint64_t prev_last = kNone;
+        for (uint32_t base = 0; base < nbuf; base += 64) {
+            const uint32_t i = base + lane;
+            const uint64_t x = i < nbuf ? sh->buf[i] : kNone;
+            uint64_t prev = i > base ? sh->buf[i - 1] : prev_last;
+            const bool first = i == 0 || prev != x;
+            const uint32_t r = below(sh->run, nr, x);
+            const bool in_run = r < nr && sh->run[r] == x;
+            const bool keep = i < nbuf && x != kNone && first && !in_run;
+            prev_last = __shfl(x, 63, 64);
+            const uint64_t m = __ballot(keep);
+            __syncthreads();
+            if (keep) sh->buf[nb2 + lanes_below64(m)] = x;
+            nb2 += (uint32_t)__popcll(m);
+            __syncthreads();
         }
+        for (uint32_t j = lane; j < nr; j += 64) {
+            const uint64_t x = sh->run[j];
+            const uint32_t r = j + below(sh->buf, nb2, x);
+            if (r < k) sh->out[r] = x;
+        }
+        for (uint32_t i = lane; i < nb2; i += 64) {
+            const uint64_t x = sh->buf[i];
+            const uint32_t r = i + below(sh->run, nr, x);
+            if (r < k) sh->out[r] = x;
+        }
+        for (uint32_t o = nr + nb2 + lane; o < k; o += 64) sh->out[o] = kNone;
+        __syncthreads();
+        for (uint32_t i = lane; i < k; i += 64) sh->run[i] = sh->out[i];
         __syncthreads();
         tau = sh->run[k - 1];
         nbuf = 0;
