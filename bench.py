@@ -465,7 +465,8 @@ def run_uneven(a, ix, rank, gdb, dev):
     gk = torch.from_numpy(k.view(np.int32)).to(dev)
     kst = int(k.max())
     t0 = time.time()
-    cfg, entry = Tuner().best(ix, gq, gw, gk, sample=min(nq, 20000))
+    # shapes timed on the whole batch: a sample's best shape is not the batch's
+    cfg, entry = Tuner().best(ix, gq, gw, gk, sample=nq)
     log(f"uneven: tuned {entry['tried']} shapes in {time.time() - t0:.1f}s: "
         f"chunk={cfg.chunk_slots} split={cfg.max_split} per_cu={cfg.blocks_per_cu} "
         f"({entry['ms']:.3f} ms vs default {entry['default_ms']:.3f} ms on {entry['sample']})")
