@@ -200,6 +200,7 @@ def main():
         log(f"calibrated fixed w = {w_fix} (calibration recall {rec_c:.4f})")
     fs, fk, fwall = timed(fixed_step(w_fix), a.steps, a.warmup)
     f_rec = recall_of(out[0])
+    f_out = (out[0].cpu().numpy().view(np.uint32), out[1].cpu().numpy().view(np.uint32))
     f_uni = int(learned.union_sizes(ix, rank, gq, w_fix).cpu().numpy().view(np.uint32).sum())
     f_ab = alg_bytes(window_slots(w_fix), f_uni)
     fixed = dict(w=w_fix, step_ms=fs, kernel_ms=fk, wall_ms=fwall, qps=a.nq / fs * 1e3,
@@ -243,7 +244,7 @@ def main():
 
     cpu = None
     if a.cpu_baseline:
-        cpu = cpu_baseline(db, q, k, w_fix, a.cpu_seconds)
+        cpu = cpu_baseline(db, q, k, w_fix, a.cpu_seconds, f_out)
 
     result = {
         "metric": "queries/s at recall@10≥0.90, learned-w vs fixed-w, 1 GPU; p50/p99 latency",
@@ -530,8 +531,9 @@ def check_truth(db, q, truth, k, m=16):
     return f"{m} queries"
 
 
-def cpu_baseline(db, q, k, w, seconds):
-    """The oracle's search timed on the host cores on a bounded query sample."""
+def cpu_baseline(db, q, k, w, seconds, gpu_out):
+    """The oracle's search timed on the host cores on a bounded query sample;
+    its results must equal the timed GPU step's (gpu_out) on every sampled query."""
     import oracle
     t0 = time.time()
     oix = oracle.Index(db)
@@ -543,14 +545,17 @@ def cpu_baseline(db, q, k, w, seconds):
     per = (time.time() - t0) / probe
     sample = int(min(len(q), max(probe, seconds / max(per, 1e-9))))
     t0 = time.time()
-    oix.search(q[:sample], k, w)
+    rid, rd = oix.search(q[:sample], k, w)
     dt = time.time() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     log(f"oracle search {sample} queries in {dt:.1f}s on {threads} threads")
+    if not ((gpu_out[0][:sample] == rid).all() and (gpu_out[1][:sample] == rd).all()):
+        raise AssertionError("the timed GPU step differs from the oracle on the sample")
+    log(f"timed GPU step equals the oracle on all {sample} sampled queries")
     return {"value": sample / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
             "sample": f"first {sample} queries of the batch at the calibrated fixed w={w}, "
                       f"k={k}, same N; the oracle's own index, built in {build:.1f}s "
-                      f"(not timed)"}
+                      f"(not timed); its results equal the timed GPU step's on all of them"}
 
 
 if __name__ == "__main__":
