@@ -67,3 +67,63 @@ def test_full_size_sampled_rows_bit_exact(full, w, path):
     key = (d.astype(np.uint64) << np.uint64(32)) | ids.astype(np.uint64)
     assert (key[:, 1:] > key[:, :-1]).all()
     assert (ids < N).all()
+
+
+def test_full_size_per_query_w_sampled_rows_bit_exact(full):
+    """The learned step's launch: a w per query (here log-uniform over the
+    spread the learned model gives at recall 0.90) on the banded path."""
+    import torch
+    gix, sc, out = full["gix"], full["sc"], full["out"]
+    rng = np.random.default_rng(1210)
+    w = np.exp(rng.uniform(np.log(16_384), np.log(65_536), size=Q)).astype(np.uint32)
+    gw = torch.from_numpy(w.view(np.int32)).to(full["gq"].device)
+    assert gix.path(Q, K, int(w.max()), sc.numel()) == PATH_BAND
+    print(f"[full] per-query w in [{w.min()}, {w.max()}]", flush=True)
+    out[0].fill_(0)
+    out[1].fill_(0)
+    gix.encode_queries(full["gq"], sc)
+    gix.search_encoded(full["gq"], K, int(w.max()), out, sc, w_per_query=gw)
+    ids, d = u32(out[0]), u32(out[1])
+    pick = full["pick"]
+    rid, rd = full["oix"].search(full["q"][pick], K, w[pick])
+    assert (ids[pick] == rid).all() and (d[pick] == rd).all()
+
+
+def test_full_size_uneven_batch_sampled_rows_bit_exact(full):
+    """The uneven step's launch: 2 x 10^5 queries, w log-uniform in [8, 512] and
+    k from {1, 10, 100} per query, the autotuned shape, captured in a HIP graph
+    and replayed; row q holds its k_q results, then empty slots."""
+    import torch
+    from paper_1209_0410_amd import datagen
+    from paper_1209_0410_amd.tune import Graph, Tuner
+    gix = full["gix"]
+    nq = 200_000
+    q = datagen.make_queries(nq, seed=datagen.SEED_UNEVEN)
+    w, k = datagen.uneven_w_k(nq)
+    dev = full["gq"].device
+    gq = torch.from_numpy(q).to(dev)
+    gw = torch.from_numpy(w.view(np.int32)).to(dev)
+    gk = torch.from_numpy(k.view(np.int32)).to(dev)
+    kst = int(k.max())
+    cfg, entry = Tuner().best(gix, gq, gw, gk, sample=nq)
+    print(f"[full] uneven shape chunk={cfg.chunk_slots} split={cfg.max_split} "
+          f"per_cu={cfg.blocks_per_cu}", flush=True)
+    sc = gix.uneven_scratch(nq, kst, cfg)
+    out = (torch.zeros((nq, kst), dtype=torch.int32, device=dev),
+           torch.zeros((nq, kst), dtype=torch.int32, device=dev))
+    g = Graph(lambda: gix.search_uneven(gq, w_per_query=gw, k_per_query=gk, k_stride=kst,
+                                        cfg=cfg, out=out, scratch=sc))
+    rng = np.random.default_rng(1211)
+    pick = np.unique(np.concatenate([np.linspace(0, nq - 1, 256).astype(np.int64),
+                                     rng.integers(0, nq, size=64)]))
+    for rep in range(2):
+        g.replay()
+        torch.cuda.synchronize()
+        ids, d = u32(out[0]), u32(out[1])
+        for kk in np.unique(k[pick]):
+            sel = pick[k[pick] == kk]
+            rid, rd = full["oix"].search(q[sel], int(kk), w[sel])
+            assert (ids[sel, :kk] == rid).all() and (d[sel, :kk] == rd).all(), (rep, kk)
+            assert (ids[sel, kk:] == 0xFFFFFFFF).all() and (d[sel, kk:] == 0xFFFFFFFF).all()
+        out[0].fill_(0)
+        out[1].fill_(0)
