@@ -540,7 +540,7 @@ def cpu_baseline(db, q, k, w, seconds, gpu_out):
     build = time.time() - t0
     log(f"oracle index build {build:.1f}s")
     t0 = time.time()
-    probe = 32
+    probe = 128
     oix.search(q[:probe], k, w)
     per = (time.time() - t0) / probe
     sample = int(min(len(q), max(probe, seconds / max(per, 1e-9))))
