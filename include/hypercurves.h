@@ -59,6 +59,8 @@ typedef enum {
 
 /* hipStream_t, passed opaquely; NULL is the null stream. */
 typedef void *hc_stream;
+/* hipEvent_t, passed opaquely. */
+typedef void *hc_event;
 
 /* Kinds of space-filling curve: the Hilbert curve of the method and, as a
  * comparison, the Z-order curve, whose key intercalates the coordinates' bits
@@ -242,6 +244,18 @@ hc_status hc_search_encoded_ex(const hc_index *idx, const uint8_t *d_queries, ui
                                uint32_t k, uint32_t w_fixed, const uint32_t *d_w,
                                uint32_t *d_out_ids, uint32_t *d_out_dists, void *d_scratch,
                                size_t scratch_bytes, uint32_t path, hc_stream stream);
+
+/* Timing aid for the search's main kernel (the distance and top-k work of
+ * Alg. 2; its helpers are left out).  With begin and end set (hipEvent_t
+ * handles created by the caller), every later hc_search_encoded(_ex) and
+ * hc_search_batch call on idx records begin on its stream just before that
+ * kernel (the gather kernel, or the banded kernel on the banded path) and end
+ * just after it, so hipEventElapsedTime(begin, end) is the kernel's duration.
+ * Both NULL turns it off.  The events stay the caller's and must outlive the
+ * calls that record them; searches on several streams at once would record
+ * the same pair.  HC_ERR_INVALID if idx is NULL or only one event is given;
+ * a failed record returns HC_ERR_HIP from the search. */
+hc_status hc_index_set_kernel_events(hc_index *idx, hc_event begin, hc_event end);
 
 /* Row store: for the banded path, each curve's rows copied in list order
  * (stored as 127 - x, the form the matrix products take) with floor(crow / 2)

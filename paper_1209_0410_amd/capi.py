@@ -60,6 +60,7 @@ SIGNATURES = {
     "hc_search_encoded": [_vp, _vp, _u32, _u32, _u32, _vp, _vp, _vp, _vp, _sz, _vp],
     "hc_search_choose_path": [_vp, _u32, _u32, _u32, _sz, ct.POINTER(_u32)],
     "hc_search_encoded_ex": [_vp, _vp, _u32, _u32, _u32, _vp, _vp, _vp, _vp, _sz, _u32, _vp],
+    "hc_index_set_kernel_events": [_vp, _vp, _vp],
     "hc_encode_keys": [_pp, _vp, _u64, _vp, _vp],
     "hc_positions": [_vp, _vp, _u32, _vp, _vp, _sz, _vp],
     "hc_candidates": [_vp, _vp, _u32, _u32, _vp, _vp, _vp, _u32, _vp, _sz, _vp],

@@ -951,11 +951,12 @@ uint64_t band_blocks(uint32_t curves, uint32_t nq, uint32_t w)
 
 // Runs the banded search with the query keys already in d_scratch.  w_fixed
 // is the window, or with per-query windows a typical one (the block size
-// follows it).
+// follows it).  ev_begin / ev_end (may be null) are recorded around the
+// banded kernel.
 hc_status band_search(const IndexView &v, const uint8_t *d_queries, uint32_t nq, uint32_t k,
                       uint32_t w_fixed, const uint32_t *d_w, uint32_t *d_out_ids,
                       uint32_t *d_out_dists, void *d_scratch, size_t scratch_bytes,
-                      hipStream_t st)
+                      hipStream_t st, hipEvent_t ev_begin, hipEvent_t ev_end)
 {
     if (k < 1 || k > (uint32_t)kBandK) return HC_ERR_UNSUPPORTED;
     const BandLayout L = band_layout(v.curves, v.n, nq);
@@ -989,8 +990,12 @@ hc_status band_search(const IndexView &v, const uint8_t *d_queries, uint32_t nq,
                        (uint64_t)L.nbuckets, nq);
     const uint64_t nt = (uint64_t)nq * v.curves;
     hipLaunchKernelGGL(k_band_scatter, dim3((uint32_t)((nt + 255) / 256)), dim3(256), 0, st, a);
+    hc_status rs = record_if(ev_begin, st);
+    if (rs != HC_OK) return rs;
     if (w_fixed < kBandWideW) launch_band<4>(v, k, nq, a, st);
     else launch_band<8>(v, k, nq, a, st);
+    rs = record_if(ev_end, st);
+    if (rs != HC_OK) return rs;
     hipLaunchKernelGGL(k_band_merge, dim3((nq + kMergeWaves - 1) / kMergeWaves),
                        dim3(64 * kMergeWaves), 0, st, a);
     return last_hip();

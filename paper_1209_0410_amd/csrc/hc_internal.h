@@ -47,6 +47,8 @@ struct hc_index {
     hc::IndexView v;
     void *base;
     size_t bytes;
+    // the caller's events, recorded around the search's main kernel when set
+    hipEvent_t kernel_begin = nullptr, kernel_end = nullptr;
 };
 
 namespace hc {
@@ -100,6 +102,12 @@ inline hc_status last_hip()
     return hipGetLastError() == hipSuccess ? HC_OK : HC_ERR_HIP;
 }
 
+// Records ev on st if it is set.
+inline hc_status record_if(hipEvent_t ev, hipStream_t st)
+{
+    return !ev || hipEventRecord(ev, st) == hipSuccess ? HC_OK : HC_ERR_HIP;
+}
+
 // Query keys for the search kernels: keys[q*curves + c].
 hc_status encode_rows(const IndexView &v, const uint8_t *rows, uint64_t nrows, Key *keys,
                       hipStream_t s);
@@ -110,7 +118,7 @@ uint64_t band_blocks(uint32_t curves, uint32_t nq, uint32_t w);   // blocks of i
 hc_status band_search(const IndexView &v, const uint8_t *d_queries, uint32_t nq, uint32_t k,
                       uint32_t w_fixed, const uint32_t *d_w, uint32_t *d_out_ids,
                       uint32_t *d_out_dists, void *d_scratch, size_t scratch_bytes,
-                      hipStream_t st);
+                      hipStream_t st, hipEvent_t ev_begin, hipEvent_t ev_end);
 
 __host__ __device__ inline bool key_less(const Key &a, const Key &b)
 {

@@ -306,14 +306,26 @@ hc_status hc_search_encoded_ex(const hc_index *idx, const uint8_t *d_queries, ui
     if (path == HC_PATH_AUTO) hc_search_choose_path(idx, nq, k, (uint32_t)hint, scratch_bytes, &path);
     if (path == HC_PATH_BAND)
         return band_search(idx->v, d_queries, nq, k, w_fixed, d_w, d_out_ids, d_out_dists,
-                           d_scratch, scratch_bytes, s);
+                           d_scratch, scratch_bytes, s, idx->kernel_begin, idx->kernel_end);
     SearchArgs a = base_args(idx, d_queries, nq, d_scratch);
     a.k = k;
     a.w_fixed = w_fixed;
     a.d_w = d_w;
     a.out_ids = d_out_ids;
     a.out_dists = d_out_dists;
-    return launch_search(a, hint, s);
+    st = record_if(idx->kernel_begin, s);
+    if (st != HC_OK) return st;
+    st = launch_search(a, hint, s);
+    if (st != HC_OK) return st;
+    return record_if(idx->kernel_end, s);
+}
+
+hc_status hc_index_set_kernel_events(hc_index *idx, hc_event begin, hc_event end)
+{
+    if (!idx || !begin != !end) return HC_ERR_INVALID;
+    idx->kernel_begin = (hipEvent_t)begin;
+    idx->kernel_end = (hipEvent_t)end;
+    return HC_OK;
 }
 
 hc_status hc_search_choose_path(const hc_index *idx, uint32_t nq, uint32_t k, uint32_t w,

@@ -196,6 +196,14 @@ class Index:
         capi.call("hc_encode_queries", self.handle, _ptr(queries), queries.shape[0],
                   _ptr(scratch), scratch.numel(), _stream())
 
+    def set_kernel_events(self, begin=None, end=None):
+        """torch.cuda.Event pair recorded around the search's main kernel by
+        later searches on this index (None, None: off).  Each event must have
+        been recorded once, so that it exists."""
+        capi.call("hc_index_set_kernel_events", self.handle,
+                  begin.cuda_event if begin is not None else None,
+                  end.cuda_event if end is not None else None)
+
     def search_encoded(self, queries, k, w, out, scratch, w_per_query=None, path=0):
         """Second launch of search(): keys already in `scratch`.  path: 0 auto,
         1 gather, 2 banded (capi.HC_PATH_*)."""

@@ -77,6 +77,7 @@ def test_search_rejects_bad_arguments_before_launch(lib):
     assert lib.hc_build_index(ct.byref(p), null, 10, null, 0, null, 0, null,
                               ct.byref(out)) == capi.HC_ERR_INVALID
     assert lib.hc_index_destroy(null) == capi.HC_ERR_INVALID
+    assert lib.hc_index_set_kernel_events(null, null, null) == capi.HC_ERR_INVALID
 
 
 def test_brute_force_validation(lib):

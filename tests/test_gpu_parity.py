@@ -192,6 +192,38 @@ def test_auto_path_matches_both(c1):
             assert (u32(x[0]) == u32(y[0])).all() and (u32(x[1]) == u32(y[1])).all()
 
 
+@pytest.mark.parametrize("path", [1, 2])
+def test_kernel_events_time_the_main_kernel_only(c1, torch_mod, path):
+    """Events recorded by the library around the search's main kernel: the
+    results do not change, the kernel's time lies inside the call's, and only
+    one event set is rejected."""
+    import ctypes as ct
+    from paper_1209_0410_amd import capi
+    torch = torch_mod
+    gix, gq = c1["gix"], c1["gq"]
+    ref = gix.search(gq, 10, 300, path=path)
+    sc = gix.scratch(gq.shape[0])
+    out = (torch.empty_like(ref[0]), torch.empty_like(ref[1]))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    st = torch.cuda.current_stream()
+    for e in ev:
+        e.record(st)
+    gix.encode_queries(gq, sc)
+    ev[0].record(st)
+    gix.set_kernel_events(ev[1], ev[2])
+    gix.search_encoded(gq, 10, 300, out, sc, path=path)
+    gix.set_kernel_events()
+    ev[3].record(st)
+    torch.cuda.synchronize()
+    call, kern = ev[0].elapsed_time(ev[3]), ev[1].elapsed_time(ev[2])
+    assert 0 < kern <= call
+    assert (u32(out[0]) == u32(ref[0])).all() and (u32(out[1]) == u32(ref[1])).all()
+    assert capi.load().hc_index_set_kernel_events(gix.handle, ct.c_void_p(ev[1].cuda_event),
+                                                 None) == capi.HC_ERR_INVALID
+    again = gix.search(gq, 10, 300, path=path)
+    assert (u32(again[0]) == u32(ref[0])).all()
+
+
 @pytest.mark.parametrize("k,w", [(10, 64), (1, 16), (16, 256), (4, 3000), (10, 0), (7, 20_000)])
 def test_rowstore_banded_bit_exact(c1, k, w):
     """With the row store attached (rows in list order, read contiguously), the
