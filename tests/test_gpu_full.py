@@ -48,19 +48,23 @@ def full(oracle):
     gix.detach_rowstore()
 
 
-@pytest.mark.parametrize("w,path", [(W_RECALL90, PATH_BAND), (64, PATH_GATHER),
-                                    (4096, PATH_BAND)])
-def test_full_size_sampled_rows_bit_exact(full, w, path):
-    gix, sc, out = full["gix"], full["sc"], full["out"]
-    assert gix.path(Q, K, w, sc.numel()) == path
-    print(f"[full] w={w} path={path} on {len(full['pick'])} sampled queries", flush=True)
+@pytest.mark.parametrize("w,path,k", [(W_RECALL90, PATH_BAND, K), (64, PATH_GATHER, K),
+                                      (4096, PATH_BAND, K), (W_RECALL90, PATH_BAND, 1),
+                                      (W_RECALL90, PATH_BAND, 16)])
+def test_full_size_sampled_rows_bit_exact(full, w, path, k):
+    import torch
+    gix, sc = full["gix"], full["sc"]
+    out = full["out"] if k == K else tuple(
+        torch.empty((Q, k), dtype=torch.int32, device=full["gq"].device) for _ in range(2))
+    assert gix.path(Q, k, w, sc.numel()) == path
+    print(f"[full] w={w} path={path} k={k} on {len(full['pick'])} sampled queries", flush=True)
     out[0].fill_(0)
     out[1].fill_(0)
     gix.encode_queries(full["gq"], sc)
-    gix.search_encoded(full["gq"], K, w, out, sc)
+    gix.search_encoded(full["gq"], k, w, out, sc)
     ids, d = u32(out[0]), u32(out[1])
     pick = full["pick"]
-    rid, rd = full["oix"].search(full["q"][pick], K, w)
+    rid, rd = full["oix"].search(full["q"][pick], k, w)
     assert (ids[pick] == rid).all() and (d[pick] == rd).all()
     # every row of the batch, sampled or not: ascending by (distance, id), no
     # repeated id, all slots filled (every window holds more than k rows)
