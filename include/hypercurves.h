@@ -252,8 +252,9 @@ hc_status hc_search_encoded_ex(const hc_index *idx, const uint8_t *d_queries, ui
  * kernel (the gather kernel, or the banded kernel on the banded path) and end
  * just after it, so hipEventElapsedTime(begin, end) is the kernel's duration.
  * Both NULL turns it off.  The events stay the caller's and must outlive the
- * calls that record them; searches on several streams at once would record
- * the same pair.  HC_ERR_INVALID if idx is NULL or only one event is given;
+ * calls that record them.  A measurement aid: it makes the handle stateful
+ * and is not thread-safe per handle (searches on several streams or threads
+ * at once would record the same pair), so leave it off outside timing runs.  HC_ERR_INVALID if idx is NULL or only one event is given;
  * a failed record returns HC_ERR_HIP from the search. */
 hc_status hc_index_set_kernel_events(hc_index *idx, hc_event begin, hc_event end);
 
@@ -321,8 +322,11 @@ hc_status hc_positions(const hc_index *idx, const uint8_t *d_queries, uint32_t n
                        hc_stream stream);
 
 /* Candidate set of every query (the union of Alg. 2), unordered: d_counts[q]
- * = its size, d_ids[q*stride ...] its ids.  Requires stride >= 16*w for every
- * query's w (HC_ERR_SIZE otherwise when d_w == NULL) and 16*w <= 65536. */
+ * = its size, d_ids[q*stride ...] its ids.  1 <= stride <= 4096 (the union is
+ * built in one LDS table; HC_ERR_UNSUPPORTED beyond).  With d_w == NULL,
+ * stride < 16 * w_fixed -> HC_ERR_SIZE.  With d_w, a query whose window slots
+ * (the sum over curves of its clamped window lengths, at most 16 w) exceed
+ * stride gets d_counts[q] = 0xFFFFFFFF and its row is left unwritten. */
 hc_status hc_candidates(const hc_index *idx, const uint8_t *d_queries, uint32_t nq,
                         uint32_t w_fixed, const uint32_t *d_w, uint32_t *d_counts,
                         uint32_t *d_ids, uint32_t stride, void *d_scratch,
@@ -415,8 +419,34 @@ hc_status hc_adam_step(float *d_master, float *d_m, float *d_v, const float *d_g
                        uint32_t t, float lr, float beta1, float beta2, float eps,
                        uint16_t *d_params_bf16, hc_stream stream);
 
+/* Preparation of the training set (caller-side steps of training, run on
+ * the device).  hc_mlp_targets: d_y[i] = log2(clamp(d_labels[i], w_min, w_max))
+ * (FP64 log2 rounded to FP32), the regression target of the MLP.
+ * hc_feature_norm: the standardisation {mean[24], std[24]} of d_feat (rows x
+ * 24) into d_norm, FP64 sums in a fixed order (deterministic), std with
+ * divisor rows - 1; a std below 1e-3 (a feature constant over the training
+ * set) becomes 1.  Errors: null pointers, rows = 0, w_min = 0 or
+ * w_min > w_max -> HC_ERR_INVALID. */
+hc_status hc_mlp_targets(const uint32_t *d_labels, uint32_t nq, uint32_t w_min, uint32_t w_max,
+                         float *d_y, hc_stream stream);
+hc_status hc_feature_norm(const float *d_feat, uint32_t rows, float *d_norm, hc_stream stream);
+
 /* FP32 -> BF16, round to nearest even. */
 hc_status hc_to_bf16(const float *d_src, uint32_t n, uint16_t *d_dst, hc_stream stream);
+
+/* ---------------------------------------------------------------------- */
+/* Measurement aid (not a step of the method)                               */
+/* ---------------------------------------------------------------------- */
+
+/* Reads `bytes` of device memory at d_buf once (16-byte aligned, bytes a
+ * multiple of 16) with coalesced 16-byte loads from `blocks` blocks of 256
+ * threads (1..65536; a few per compute unit fill the device), and writes one
+ * word per block to d_sink[0 .. blocks) (the XOR of what the block read), so
+ * that no load is dropped.  Timing it gives the streaming-read bandwidth the
+ * device achieves.  Errors: null or misaligned pointers, bytes not a multiple
+ * of 16, blocks out of range -> HC_ERR_INVALID. */
+hc_status hc_read_probe(const void *d_buf, size_t bytes, uint32_t *d_sink, uint32_t blocks,
+                        hc_stream stream);
 
 #ifdef __cplusplus
 }

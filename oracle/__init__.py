@@ -58,7 +58,7 @@ def lib():
     if _LIB is None:
         if not os.path.exists(_build.LIB):
             _build.build()
-        L = ct.CDLL(_build.LIB)
+        L = ct.CDLL(_build.lib_path())
         for name, args in _SIGS.items():
             fn = getattr(L, name)
             fn.argtypes = args
@@ -67,8 +67,22 @@ def lib():
         L.hco_lower_bound.restype = ct.c_int64
         L.hco_mlp_nparams.argtypes = [_int, _int, _int]
         L.hco_mlp_nparams.restype = ct.c_int64
+        L.hco_set_threads.argtypes = [_int]
+        L.hco_set_threads.restype = None
+        L.hco_threads.argtypes = []
+        L.hco_threads.restype = _int
         _LIB = L
     return _LIB
+
+
+def set_threads(t):
+    """Threads of the oracle's parallel loops from now on (t >= 1)."""
+    lib().hco_set_threads(int(t))
+
+
+def threads():
+    """Threads the oracle's parallel loops use."""
+    return int(lib().hco_threads())
 
 
 def _check(rc, name):

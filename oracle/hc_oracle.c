@@ -44,10 +44,23 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#include <omp.h>
 
 typedef unsigned __int128 u128;
 
 #define PAD 0xFFFFFFFFu
+
+/* Threads of the parallel loops over queries (timing of the CPU baseline):
+ * hco_set_threads(t) for t >= 1; hco_threads() is the count in use. */
+void hco_set_threads(int t)
+{
+    if (t >= 1) omp_set_num_threads(t);
+}
+
+int hco_threads(void)
+{
+    return omp_get_max_threads();
+}
 
 /* ------------------------------------------------------------------------ */
 /* Hilbert extended key (Sec. 2.2.1)                                         */

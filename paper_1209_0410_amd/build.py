@@ -11,7 +11,7 @@ LIB = os.path.join(HERE, "libhypercurves.so")
 OBJDIR = os.path.join(HERE, "_build")
 
 SOURCES = ["hc_encode.hip", "hc_build.hip", "hc_search.hip", "hc_brute.hip", "hc_learn.hip",
-           "hc_uneven.hip", "hc_band.hip", "hc_host.hip"]
+           "hc_uneven.hip", "hc_band.hip", "hc_host.hip", "hc_probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -77,7 +77,10 @@ SIGNATURES = {
     "hc_adam_step": [_vp, _vp, _vp, _vp, _u32, _u32, ct.c_float, ct.c_float, ct.c_float,
                      ct.c_float, _vp, _vp],
     "hc_to_bf16": [_vp, _u32, _vp, _vp],
+    "hc_mlp_targets": [_vp, _u32, _u32, _u32, _vp, _vp],
+    "hc_feature_norm": [_vp, _u32, _vp, _vp],
     "hc_uneven_scratch_bytes": [_vp, _u32, _u32, ct.POINTER(hc_uneven_cfg), ct.POINTER(_sz)],
+    "hc_read_probe": [_vp, _sz, _vp, _u32, _vp],
     "hc_search_uneven": [_vp, _vp, _u32, _u32, _vp, _u32, _vp, _u32, _vp, _vp, _vp, _sz,
                          ct.POINTER(hc_uneven_cfg), _vp],
 }

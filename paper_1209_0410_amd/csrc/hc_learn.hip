@@ -518,6 +518,58 @@ __global__ __launch_bounds__(256) void k_to_bf16(const float *src, uint32_t n, u
     if (i < n) dst[i] = f32_to_bf16(src[i]);
 }
 
+// Training targets: y = log2(clamp(label, w_min, w_max)), the label's log
+// taken in FP64 and rounded to FP32.
+__global__ __launch_bounds__(256) void k_targets(const uint32_t *labels, uint32_t nq,
+                                                 uint32_t w_min, uint32_t w_max, float *y)
+{
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= nq) return;
+    uint32_t l = labels[i];
+    l = l < w_min ? w_min : (l > w_max ? w_max : l);
+    y[i] = (float)log2((double)l);
+}
+
+// Standardisation of one feature per block: mean and standard deviation
+// (divisor rows - 1) over the rows, summed in FP64 in a fixed order (thread t
+// takes rows t, t + 256, ..., then a fixed tree), so the result is
+// deterministic.  A deviation below 1e-3 (a feature that does not vary) is
+// replaced by 1, so that unseen values stay moderate.
+constexpr int kNormThreads = 256;
+__global__ __launch_bounds__(kNormThreads) void k_feature_norm(const float *x, uint32_t rows,
+                                                               float *norm)
+{
+    __shared__ double sh[kNormThreads];
+    const uint32_t f = blockIdx.x, t = threadIdx.x;
+    double s = 0.0;
+    for (uint32_t r = t; r < rows; r += kNormThreads) s += (double)x[(uint64_t)r * kIn + f];
+    sh[t] = s;
+    __syncthreads();
+    for (int m = kNormThreads / 2; m > 0; m >>= 1) {
+        if ((int)t < m) sh[t] += sh[t + m];
+        __syncthreads();
+    }
+    const double mean = sh[0] / (double)rows;
+    __syncthreads();
+    double v = 0.0;
+    for (uint32_t r = t; r < rows; r += kNormThreads) {
+        const double d = (double)x[(uint64_t)r * kIn + f] - mean;
+        v += d * d;
+    }
+    sh[t] = v;
+    __syncthreads();
+    for (int m = kNormThreads / 2; m > 0; m >>= 1) {
+        if ((int)t < m) sh[t] += sh[t + m];
+        __syncthreads();
+    }
+    if (t == 0) {
+        double sd = rows > 1 ? sqrt(sh[0] / (double)(rows - 1)) : 0.0;
+        if (!(sd >= 1e-3)) sd = 1.0;
+        norm[f] = (float)mean;
+        norm[kIn + f] = (float)sd;
+    }
+}
+
 static hc_status learn_common(const hc_index *idx, const uint8_t *d_queries, uint32_t nq,
                               void *d_scratch, size_t scratch_bytes, hipStream_t s,
                               LearnArgs *a)
@@ -694,6 +746,24 @@ hc_status hc_adam_step(float *d_master, float *d_m, float *d_v, const float *d_g
     hipLaunchKernelGGL(k_adam, dim3((np + 255) / 256), dim3(256), 0, (hipStream_t)stream,
                        d_master, d_m, d_v, d_grad, np, lr, beta1, beta2, eps, c1, c2,
                        d_params_bf16);
+    return last_hip();
+}
+
+hc_status hc_mlp_targets(const uint32_t *d_labels, uint32_t nq, uint32_t w_min, uint32_t w_max,
+                         float *d_y, hc_stream stream)
+{
+    if (!d_labels || !d_y || w_min < 1 || w_min > w_max) return HC_ERR_INVALID;
+    if (nq == 0) return HC_OK;
+    hipLaunchKernelGGL(k_targets, dim3((nq + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                       d_labels, nq, w_min, w_max, d_y);
+    return last_hip();
+}
+
+hc_status hc_feature_norm(const float *d_feat, uint32_t rows, float *d_norm, hc_stream stream)
+{
+    if (!d_feat || !d_norm || rows < 1) return HC_ERR_INVALID;
+    hipLaunchKernelGGL(k_feature_norm, dim3(kIn), dim3(kNormThreads), 0, (hipStream_t)stream,
+                       d_feat, rows, d_norm);
     return last_hip();
 }
 

@@ -120,18 +120,21 @@ class WModel:
         self.w_hint = 64        # typical predicted w (sizes the search's execution path)
 
     def targets(self, label):
-        """y = log2(clamp(label, w_min, w_max)) as float32 (host math on labels)."""
-        lab = label.to(torch.int64).clamp(self.w_min, self.w_max)
-        return torch.log2(lab.to(torch.float64)).to(torch.float32)
+        """y = log2(clamp(label, w_min, w_max)) as float32 (hc_mlp_targets)."""
+        label = label.contiguous()
+        y = torch.empty(label.shape[0], dtype=torch.float32, device=label.device)
+        capi.call("hc_mlp_targets", _ptr(label), label.shape[0], self.w_min, self.w_max,
+                  _ptr(y), _stream())
+        return y
 
     def set_norm(self, feats):
-        """Standardisation from training features; a feature that does not vary
-        in training keeps unit scale (so unseen values stay moderate)."""
-        f = feats.to(torch.float64)
-        mean = f.mean(0)
-        std = f.std(0)
-        std = torch.where(std < 1e-3, torch.ones_like(std), std)
-        self.norm = torch.cat([mean, std]).to(torch.float32).contiguous()
+        """Standardisation from training features (hc_feature_norm); a feature
+        that does not vary in training keeps unit scale (so unseen values stay
+        moderate)."""
+        feats = feats.contiguous()
+        norm = torch.empty(2 * FEATURES, dtype=torch.float32, device=feats.device)
+        capi.call("hc_feature_norm", _ptr(feats), feats.shape[0], _ptr(norm), _stream())
+        self.norm = norm
 
     def train(self, feats, y, epochs=20, batch=4096, lr=1e-3, seed=0, log=None):
         """Adam on the MSE of y, batches drawn in a seeded order; returns losses."""
@@ -198,18 +201,31 @@ class WModel:
 def recall_at_k(ids, truth):
     """Mean of |approx ∩ exact| / k over the queries (numpy uint32 arrays)."""
     k = truth.shape[1]
-    hits = [len(set(a.tolist()) & set(b.tolist()) - {0xFFFFFFFF}) for a, b in zip(ids, truth)]
-    return float(np.mean(hits)) / k
+    ids = np.asarray(ids, np.uint32)[:, :k]
+    truth = np.asarray(truth, np.uint32)
+    # ids within a row are distinct (as are the truth's), so each match counts once
+    hit = (ids[:, :, None] == truth[:, None, :]).any(axis=2) & (ids != 0xFFFFFFFF)
+    return float(hit.sum(axis=1).mean()) / k
+
+
+def quick_path(ix: Index, nq, k, w):
+    """The faster execution path for a calibration batch: banded when each list
+    entry lies in several of the batch's windows (k <= 16), whatever the block
+    count (both paths give the same results; the automatic choice also wants
+    enough blocks to fill the device, which a small batch lacks)."""
+    return capi.HC_PATH_BAND if (k <= 16 and 2.0 * w * nq >= 3.5 * ix.n) else capi.HC_PATH_GATHER
 
 
 def calibrate_delta(ix: Index, model: WModel, queries, feats, truth, k, target=0.90,
                     lo=-4.0, hi=8.0, iters=12):
     """Smallest delta (bisection) whose searches reach mean recall@k >= target."""
     truth_np = truth.cpu().numpy().view(np.uint32)
+    nq = queries.shape[0]
 
     def rec(d):
         w = model.windows(feats, d)
-        ids, _ = ix.search(queries, k, int(w.float().mean().item()) or 64, w_per_query=w)
+        wm = int(w.float().mean().item()) or 64
+        ids, _ = ix.search(queries, k, wm, w_per_query=w, path=quick_path(ix, nq, k, wm))
         return recall_at_k(ids.cpu().numpy().view(np.uint32), truth_np)
 
     if rec(hi) < target:
@@ -249,9 +265,10 @@ def calibrate_fixed_w(ix: Index, queries, truth, k, target=0.90, lo=1, hi=1 << 1
     recall@k >= target; the recall never drops as w grows (the candidate sets
     are nested and every true neighbour found stays among the k nearest)."""
     truth_np = truth.cpu().numpy().view(np.uint32)
+    nq = queries.shape[0]
 
     def rec(w):
-        ids, _ = ix.search(queries, k, int(w))
+        ids, _ = ix.search(queries, k, int(w), path=quick_path(ix, nq, k, w))
         return recall_at_k(ids.cpu().numpy().view(np.uint32), truth_np)
 
     if rec(hi) < target:

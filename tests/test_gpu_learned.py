@@ -288,3 +288,25 @@ def test_learned_vs_fixed_at_equal_cost():
     print(f"[gain] mean w {wv.mean():.1f}: recall learned {rec['learned']:.4f}, "
           f"fixed {rec['fixed']:.4f}, gain {rec['learned'] - rec['fixed']:+.4f}", flush=True)
     assert 0.05 < rec["learned"] < 1 and 0.05 < rec["fixed"] < 1
+
+
+def test_training_set_preparation(setup):
+    """hc_mlp_targets and hc_feature_norm against numpy in FP64: targets exact
+    to FP32 rounding of log2 of the clamped integer; mean and std (divisor
+    rows - 1) within FP32 rounding; a constant feature keeps scale 1."""
+    import torch
+    from paper_1209_0410_amd import learned
+    m = learned.WModel(torch.device("cuda:0"), seed=1, w_min=8, w_max=1 << 17)
+    lab = np.array([0, 1, 7, 8, 9, 1000, 131071, 131072, 131073, 1 << 30], np.uint32)
+    y = m.targets(torch.from_numpy(lab.view(np.int32)).cuda()).cpu().numpy()
+    ref = np.log2(np.clip(lab.astype(np.float64), 8, 1 << 17)).astype(np.float32)
+    assert (y == ref).all()
+    f = learned.features(setup["gix"], setup["gq"], 10)
+    m.set_norm(f)
+    norm = m.norm.cpu().numpy()
+    x = f.cpu().numpy().astype(np.float64)
+    mean, std = x.mean(0), x.std(0, ddof=1)
+    std = np.where(std < 1e-3, 1.0, std)
+    assert np.allclose(norm[:24], mean, rtol=1e-6, atol=1e-6)
+    assert np.allclose(norm[24:], std, rtol=1e-6, atol=1e-6)
+    assert norm[24 + 20] == 1.0                     # log2 k: constant at k = 10

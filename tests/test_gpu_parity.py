@@ -88,6 +88,27 @@ def test_candidate_sets_bit_exact(c1, w):
         assert (np.sort(ids[i, :counts[i]]) == r).all()
 
 
+def test_candidate_limits(c1, torch_mod):
+    """The export's limits as the header states them: stride above 4096 is
+    refused; with a w per query, a query whose window slots exceed the stride
+    is flagged 0xFFFFFFFF and the others are exact."""
+    from paper_1209_0410_amd import capi
+    with pytest.raises(capi.HcError) as e:
+        c1["gix"].candidates(c1["gq"][:4], 300, stride=4097)
+    assert e.value.status == capi.HC_ERR_UNSUPPORTED
+    with pytest.raises(capi.HcError) as e:
+        c1["gix"].candidates(c1["gq"][:4], 300, stride=4000)
+    assert e.value.status == capi.HC_ERR_SIZE
+    w = np.array([16, 300, 256, 1], np.uint32)        # 16 * 300 > 4096 slots
+    gw = torch_mod.from_numpy(w.view(np.int32)).cuda()
+    counts, ids = c1["gix"].candidates(c1["gq"][:4], 0, w_per_query=gw, stride=4096)
+    counts, ids = u32(counts), u32(ids)
+    assert counts[1] == U32
+    for i in (0, 2, 3):
+        ref = c1["oix"].candidates(c1["q"][i:i + 1], int(w[i]))[0]
+        assert counts[i] == len(ref) and (np.sort(ids[i, :counts[i]]) == ref).all()
+
+
 @pytest.mark.parametrize("k,w", [(10, 64), (1, 16), (10, 1), (16, 256), (17, 64),
                                  (100, 64), (256, 40), (10, 300), (10, 600), (5, 2000)])
 def test_search_bit_exact(c1, k, w):

@@ -248,3 +248,85 @@ def test_features_match_python_bigint(oracle, tiny):
             g = [np.log2(1.0 + float(K(c, cl(pos[i, c] + s - 1)) - K(c, cl(pos[i, c] - s))))
                  for c in range(8)]
             assert f[i, 21 + j] == pytest.approx(max(g), rel=1e-12)
+
+
+def _hand_built_index(oracle, key_of_entry, n):
+    """An oracle index whose lists are written by hand: curve c's entry i has
+    key key_of_entry(c, i) (integers, ascending in i) and id (i - 100 + c) mod n
+    (so entry 100 of curve c holds id c).  The query's subspace of curve c is
+    the point the Hilbert decode gives for key 100 (c + 1), so its key there is
+    exactly that integer.  Database row j < 8 is the query with dim 127 raised
+    by j + 1 (squared distance (j + 1)^2); the other rows are far."""
+    p = oracle.Params()
+    q = np.zeros(128, np.uint8)
+    for c in range(8):
+        pt = oracle.hilbert_decode(np.array([0], np.uint64),
+                                   np.array([100 * (c + 1)], np.uint64), 16, 8)[0]
+        q[16 * c:16 * c + 16] = pt
+    hi, lo = oracle.keys(q[None], p)
+    assert all(oracle.key_int(hi[0, c], lo[0, c]) == 100 * (c + 1) for c in range(8))
+    db = np.tile(q, (n, 1))
+    db[:, 0] = np.minimum(db[:, 0].astype(np.int64) + 60, 255).astype(np.uint8)
+    for j in range(8):
+        db[j] = q
+        db[j, 127] = q[127] + j + 1
+    ix = oracle.Index.__new__(oracle.Index)
+    ix.p, ix.db, ix.n = p, np.ascontiguousarray(db), n
+    ix.hi = np.zeros((8, n), np.uint64)
+    ix.lo = np.zeros((8, n), np.uint64)
+    ix.ids = np.zeros((8, n), np.uint32)
+    for c in range(8):
+        for i in range(n):
+            kv = key_of_entry(c, i)
+            ix.hi[c, i] = kv >> 64
+            ix.lo[c, i] = kv & ((1 << 64) - 1)
+            ix.ids[c, i] = (i - 100 + c) % n
+    return ix, q
+
+
+def test_features_hand_built_interior(oracle):
+    """Curve c's keys are (c + 1) * i for i = 0..n-1 (curve 0: the integers
+    0..n-1); the query's key is 100 (c + 1), so its place is 100 on every curve.
+    The expected 24 features are written out from that construction, not from
+    the feature formulas."""
+    n = 200
+    ix, q = _hand_built_index(oracle, lambda c, i: (c + 1) * i, n)
+    assert (ix.positions(q[None]) == 100).all()
+    f = ix.features(q[None], 10)[0]
+    L = np.log2
+    cs = np.arange(1, 9)
+    # key gaps to the entries at offsets -64, -8, -1 and +1, +8, +64, which sit
+    # 64, 8, 1, 0, 7 and 63 entries from the place: gap = (c + 1) * that
+    expect_min = [L(65), L(9), L(2), 0.0, L(8), L(64)]
+    expect_mean = [np.mean(L(1 + cs * d)) for d in (64, 8, 1, 0, 7, 63)]
+    # first candidates: row c, at squared distance (c + 1)^2
+    expect_first = list(L(1 + cs ** 2))
+    # spans: entries pos - s .. pos + s - 1 cover 2s - 1 steps; the widest
+    # curve (spacing 8) gives the max
+    expect_span = [L(1 + 8 * 1), L(1 + 8 * 15), L(1 + 8 * 127)]
+    expect = expect_min + expect_mean + expect_first + [L(10)] + expect_span
+    assert f.shape == (24,)
+    assert np.allclose(f, expect, rtol=0, atol=1e-12), (f, expect)
+
+
+def test_features_hand_built_list_start(oracle):
+    """Keys (c + 1) (i + 1) + 100 (c + 1): every key is above the query's, so its
+    place is 0 and the entries before it clamp to entry 0."""
+    n = 200
+    ix, q = _hand_built_index(oracle, lambda c, i: (c + 1) * (i + 1) + 100 * (c + 1), n)
+    assert (ix.positions(q[None]) == 0).all()
+    f = ix.features(q[None], 1)[0]
+    L = np.log2
+    cs = np.arange(1, 9)
+    # entries at -64, -8, -1 and +1 all clamp to or are entry 0 (gap c + 1);
+    # +8 is entry 7 (gap 8 (c + 1)), +64 is entry 63 (gap 64 (c + 1))
+    steps = (1, 1, 1, 1, 8, 64)
+    expect_min = [L(1 + s) for s in steps]
+    expect_mean = [np.mean(L(1 + cs * s)) for s in steps]
+    # entry 0 of curve c holds id (c - 100) mod n, one of the far rows: query
+    # plus 60 in dim 0
+    expect_first = [L(1 + 60 ** 2)] * 8
+    # spans: entry s - 1 minus entry 0 (the lower end clamps): (c + 1)(s - 1)
+    expect_span = [0.0, L(1 + 8 * 7), L(1 + 8 * 63)]
+    expect = expect_min + expect_mean + expect_first + [0.0] + expect_span
+    assert np.allclose(f, expect, rtol=0, atol=1e-12), (f, expect)
