@@ -209,6 +209,27 @@ hc_status hc_search_batch(const hc_index *idx, const uint8_t *d_queries, uint32_
                           uint32_t *d_out_ids, uint32_t *d_out_dists,
                           void *d_scratch, size_t scratch_bytes, hc_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * search as hc_search_batch on the gather path (HC_PATH_GATHER, identical
+ * results), with the query keys kept in a scratch array the library owns, so
+ * the caller passes only the queries and the outputs.  The array,
+ * HC_NOALLOC_SCRATCH_BYTES (4 MiB), is a static device array: each GPU the
+ * library runs on holds its own copy until the process ends.  Its address on
+ * the current device is looked up on the first call on that device (the
+ * index's buffers must be on the current device).  Nothing is allocated:
+ * no hipMalloc or hipFree, and no library routine that allocates.  Limit:
+ * nq * curves * 16 <= HC_NOALLOC_SCRATCH_BYTES (32,768 queries with 8
+ * curves), else HC_ERR_SIZE.  Every call on a GPU shares that GPU's array:
+ * calls that overlap on one GPU (several streams or threads) race and must be
+ * serialised by the caller.  Other arguments and errors as in
+ * hc_search_batch; a failed symbol lookup returns HC_ERR_HIP. */
+#define HC_NOALLOC_SCRATCH_BYTES (4u << 20)
+hc_status hc_search_batch_noalloc(const hc_index *idx, const uint8_t *d_queries, uint32_t nq,
+                                  uint32_t k, uint32_t w_fixed, const uint32_t *d_w,
+                                  uint32_t *d_out_ids, uint32_t *d_out_dists,
+                                  hc_stream stream);
+
 /* The two launches of hc_search_batch, for callers that time or overlap them:
  * hc_encode_queries writes the query keys into d_scratch (the keys step of
  * Alg. 2); hc_search_encoded runs the rest of Alg. 2 with the keys already in

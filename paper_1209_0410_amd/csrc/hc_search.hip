@@ -26,6 +26,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "hc_device.h"
 
@@ -267,6 +268,33 @@ static SearchArgs base_args(const hc_index *idx, const uint8_t *d_queries, uint3
     return a;
 }
 
+// Scratch of hc_search_batch_noalloc: the query keys, in a device array the
+// library owns (one copy per GPU, kept until the process ends).  Host code
+// never passes the array's name to a kernel or a copy: on the host it is only
+// a stand-in for the symbol.  The device address comes from
+// hipGetSymbolAddress, once per device, and is kept per device.
+static __device__ __align__(256) uint8_t scratch[HC_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// The address of `scratch` on the current device.
+static hc_status noalloc_scratch(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return HC_ERR_HIP;
+    if (dev < 0 || dev >= kMaxDevices) return HC_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return HC_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return HC_OK;
+}
+
 }  // namespace hc
 
 using namespace hc;
@@ -362,6 +390,25 @@ hc_status hc_search_batch(const hc_index *idx, const uint8_t *d_queries, uint32_
     if (st != HC_OK) return st;
     return hc_search_encoded(idx, d_queries, nq, k, w_fixed, d_w, d_out_ids, d_out_dists,
                              d_scratch, scratch_bytes, stream);
+}
+
+hc_status hc_search_batch_noalloc(const hc_index *idx, const uint8_t *d_queries, uint32_t nq,
+                                  uint32_t k, uint32_t w_fixed, const uint32_t *d_w,
+                                  uint32_t *d_out_ids, uint32_t *d_out_dists,
+                                  hc_stream stream)
+{
+    if (!idx || k < 1 || k > HC_K_MAX || !d_out_ids || !d_out_dists) return HC_ERR_INVALID;
+    if (nq == 0) return HC_OK;
+    if (sizeof(Key) * (uint64_t)nq * idx->v.curves > HC_NOALLOC_SCRATCH_BYTES)
+        return HC_ERR_SIZE;
+    void *s = nullptr;
+    const hc_status st = noalloc_scratch(&s);
+    if (st != HC_OK) return st;
+    // every key the search reads is written first: nothing to clear
+    const hc_status se = hc_encode_queries(idx, d_queries, nq, s, HC_NOALLOC_SCRATCH_BYTES, stream);
+    if (se != HC_OK) return se;
+    return hc_search_encoded_ex(idx, d_queries, nq, k, w_fixed, d_w, d_out_ids, d_out_dists, s,
+                                HC_NOALLOC_SCRATCH_BYTES, HC_PATH_GATHER, stream);
 }
 
 hc_status hc_positions(const hc_index *idx, const uint8_t *d_queries, uint32_t nq,
