@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--train", type=int, default=1_000_000, help="0 = no learned w")
     ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--confidence", type=lambda x: [float(v) for v in x.split(",")],
+                    default=[1.0, 0.5, 0.25, 0.0],
+                    help="weights of the MLP's prediction against its training mean to try")
     ap.add_argument("--calib-q", type=int, default=10_000)
     ap.add_argument("--w-max", type=int, default=1 << 20)
     ap.add_argument("--w-fixed", type=int, default=0,
@@ -444,15 +447,35 @@ def run_learned(a, ix, rank, gdb, gq, gcq, ctruth, out, sc, recall_of, work, str
     torch.cuda.synchronize()
     train_s = time.time() - t0
     log(f"trained {a.epochs} epochs in {train_s:.1f}s, loss {losses[0]:.3f} -> {losses[-1]:.3f}")
+    # a batch of training queries (as many as the evaluation batch) on which
+    # the confidence in the prediction is chosen by speed
+    gsel = gtq[:a.nq].clone()
     del gtq, ttruth, feats, y
     cfeats = learned.features(ix, gcq, k)
-    t0 = time.time()
-    delta, rec_c = learned.calibrate_delta(ix, model, gcq, cfeats, ctruth, k, CALIB_TARGET)
-    model.delta = delta
-    log(f"calibrated delta = {delta:.3f} (calibration recall {rec_c:.4f}) in "
-        f"{time.time() - t0:.1f}s")
     feats_b = torch.empty((a.nq, learned.FEATURES), dtype=torch.float32, device=dev)
     wq = torch.empty(a.nq, dtype=torch.int32, device=dev)
+    # For each confidence lam (prediction y_mean + lam (y - y_mean)): the
+    # offset delta that reaches the recall target on the calibration queries,
+    # then the step time on the training batch.  The fastest lam is kept.
+    t0 = time.time()
+    grid = []
+    for lam in a.confidence:
+        model.set_confidence(lam)
+        d, r = learned.calibrate_delta(ix, model, gcq, cfeats, ctruth, k, CALIB_TARGET)
+        model.delta = d
+        ts = summary(timed(learned_step(ix, model, gsel, k, out, sc, feats_b, wq), 3, 1,
+                           stream))
+        grid.append(dict(confidence=lam, delta=d, calib_recall=r, w_hint=model.w_hint,
+                         train_batch_ms=ts["step_ms"], mean_w=float(u32(wq).mean())))
+        log(f"confidence {lam:.2f}: delta {d:.3f} (calibration recall {r:.4f}), mean w "
+            f"{grid[-1]['mean_w']:.0f}, {ts['step_ms']:.3f} ms on {a.nq} training queries")
+    best = min(grid, key=lambda g: g["train_batch_ms"])
+    model.set_confidence(best["confidence"])
+    model.delta, model.w_hint = best["delta"], best["w_hint"]
+    delta, rec_c = best["delta"], best["calib_recall"]
+    del gsel
+    log(f"chosen confidence {best['confidence']:.2f}, delta = {delta:.3f} in "
+        f"{time.time() - t0:.1f}s")
     lt = summary(timed(learned_step(ix, model, gq, k, out, sc, feats_b, wq), a.steps, a.warmup,
                        stream))
     lout = (u32(out[0]), u32(out[1]))
@@ -462,6 +485,7 @@ def run_learned(a, ix, rank, gdb, gq, gcq, ctruth, out, sc, recall_of, work, str
                qps=a.nq / lt["step_ms"] * 1e3, recall=recall_of(out[0]), delta=delta,
                calib_recall=rec_c, mean_w=float(wv.mean()),
                w_pct=np.percentile(wv, [10, 50, 90, 99]).tolist(), **lw,
+               confidence=best["confidence"], confidence_grid=grid,
                train_queries=a.train, epochs=a.epochs, loss=[losses[0], losses[-1]],
                train_s=train_s, label_pct=np.percentile(labs, [10, 50, 90]).tolist())
     log(f"learned: {lt['step_ms']:.3f} ms/step [{lt['step_ms_min']:.3f}, "

@@ -118,6 +118,8 @@ class WModel:
         self.delta = 0.0
         self.w_min, self.w_max = int(w_min), int(w_max)
         self.w_hint = 64        # typical predicted w (sizes the search's execution path)
+        self.confidence = 1.0   # weight of the prediction against the training mean
+        self.y_mean = 0.0       # mean of the training targets
 
     def targets(self, label):
         """y = log2(clamp(label, w_min, w_max)) as float32 (hc_mlp_targets)."""
@@ -149,6 +151,7 @@ class WModel:
         v = torch.zeros_like(grad)
         loss = torch.zeros(1, dtype=torch.float32, device=self.device)
         rng = np.random.default_rng(seed)
+        self.y_mean = float(np.mean(y.cpu().numpy(), dtype=np.float64))
         t = 0
         losses = []
         for ep in range(epochs):
@@ -167,6 +170,21 @@ class WModel:
             if log:
                 log(f"epoch {ep} loss {losses[-1]:.4f}")
         return losses
+
+    def set_confidence(self, lam):
+        """Inference weights whose output is y_mean + lam * (y - y_mean): the
+        last layer is linear, so its weights are scaled by lam and its bias
+        moved toward the training mean (lam = 1: the trained network; lam = 0:
+        one w for every query, 2^(y_mean + delta)).  A prediction that carries
+        little information about the labels is worth less than its spread
+        costs; the calibration picks lam."""
+        lam = float(lam)
+        p = self.master.detach().cpu().numpy().astype(np.float64).copy()
+        w3 = slice(NPARAMS - 1 - DIMS[2], NPARAMS - 1)
+        p[w3] *= lam
+        p[NPARAMS - 1] = lam * p[NPARAMS - 1] + (1.0 - lam) * self.y_mean
+        self.bf16 = to_bf16(torch.from_numpy(p.astype(np.float32)).to(self.device))
+        self.confidence = lam
 
     def predict(self, feats):
         """y = MLP(standardised features), float32 (nq,)."""
@@ -188,7 +206,8 @@ class WModel:
 
     def state(self):
         return {"master": self.master.cpu().numpy(), "norm": self.norm.cpu().numpy(),
-                "delta": self.delta, "w_min": self.w_min, "w_max": self.w_max}
+                "delta": self.delta, "w_min": self.w_min, "w_max": self.w_max,
+                "confidence": self.confidence, "y_mean": self.y_mean}
 
     def load_state(self, st):
         self.master = torch.from_numpy(np.asarray(st["master"], np.float32)).to(self.device)
@@ -196,6 +215,8 @@ class WModel:
         self.norm = torch.from_numpy(np.asarray(st["norm"], np.float32)).to(self.device)
         self.delta = float(st["delta"])
         self.w_min, self.w_max = int(st["w_min"]), int(st["w_max"])
+        self.y_mean = float(st.get("y_mean", 0.0))
+        self.set_confidence(st.get("confidence", 1.0))
 
 
 def recall_at_k(ids, truth):
