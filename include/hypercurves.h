@@ -186,11 +186,17 @@ hc_status hc_index_info(const hc_index *idx, uint64_t *n, uint32_t *curves);
 /* Search (Alg. 2)                                                         */
 /* ---------------------------------------------------------------------- */
 
-/* Scratch bytes hc_search_batch needs for nq queries on either path (also
- * valid for hc_positions, hc_candidates and the learned-depth entry points).
- * A smaller buffer of at least nq * curves * 16 bytes restricts the search to
- * the gather path. */
+/* Scratch bytes hc_search_batch needs for nq queries on either path with
+ * k <= 16 (also valid for hc_positions, hc_candidates and the learned-depth
+ * entry points).  A smaller buffer of at least nq * curves * 16 bytes
+ * restricts the search to the gather path.
+ * hc_search_scratch_bytes_k: the same for k up to k_max (1..HC_K_MAX): with
+ * 16 < k_max the banded path's two-pass buffers are included (k up to
+ * HC_BAND_K_MAX, row store attached; about 8 KiB + 512 B x curves per query).
+ * Errors: null pointers, k_max outside [1, HC_K_MAX] -> HC_ERR_INVALID. */
 hc_status hc_search_scratch_bytes(const hc_index *idx, uint32_t nq, size_t *bytes);
+hc_status hc_search_scratch_bytes_k(const hc_index *idx, uint32_t nq, uint32_t k_max,
+                                    size_t *bytes);
 
 /* Alg. 2 for a batch of queries (d_queries: nq x 128 uint8).  Per query and
  * curve c: key = C^-1(projection onto c); pos_c = number of list entries whose
@@ -250,12 +256,21 @@ hc_status hc_search_encoded(const hc_index *idx, const uint8_t *d_queries, uint3
  *                  streamed row come from the int8 matrix cores, and each
  *                  query keeps the entries inside its own window (for large
  *                  batches with large windows, where one list entry lies in
- *                  many windows).  k <= 16.
+ *                  many windows).  k <= 16 in one pass.  With the row store
+ *                  attached, 16 < k <= HC_BAND_K_MAX in two passes: the
+ *                  first keeps the 16 nearest of each half of every window's
+ *                  rows, whose k-th nearest distinct key bounds the result;
+ *                  the second collects every pair of the windows at or below
+ *                  that bound (up to 1,024 per query), whose k nearest
+ *                  distinct keys are the result.  A query left without a
+ *                  bound or with more pairs is answered by the gather kernel.
  *  HC_PATH_AUTO:   banded when 2 w nq >= 3.5 n (w = w_fixed or the hint), the
  *                  batch makes at least 512 blocks (nq / 128 or nq / 256 per
- *                  curve, times curves), k <= 16
- *                  and the scratch holds hc_search_scratch_bytes; else gather.
+ *                  curve, times curves), k <= 16 (or k <= HC_BAND_K_MAX with
+ *                  the row store) and the scratch holds
+ *                  hc_search_scratch_bytes_k for that k; else gather.
  * hc_search_encoded is hc_search_encoded_ex with HC_PATH_AUTO. */
+#define HC_BAND_K_MAX 128u
 #define HC_PATH_AUTO 0u
 #define HC_PATH_GATHER 1u
 #define HC_PATH_BAND 2u

@@ -14,6 +14,7 @@ HC_OK, HC_ERR_INVALID, HC_ERR_SIZE, HC_ERR_HIP, HC_ERR_UNSUPPORTED = 0, -1, -2, 
 HC_K_MAX = 256
 HC_PATH_AUTO, HC_PATH_GATHER, HC_PATH_BAND = 0, 1, 2
 HC_NOALLOC_SCRATCH_BYTES = 4 << 20
+HC_BAND_K_MAX = 128
 
 
 class HcError(RuntimeError):
@@ -56,6 +57,7 @@ SIGNATURES = {
     "hc_index_curve": [_vp, _u32, ct.POINTER(_vp), ct.POINTER(_vp)],
     "hc_index_info": [_vp, ct.POINTER(_u64), ct.POINTER(_u32)],
     "hc_search_scratch_bytes": [_vp, _u32, ct.POINTER(_sz)],
+    "hc_search_scratch_bytes_k": [_vp, _u32, _u32, ct.POINTER(_sz)],
     "hc_search_batch": [_vp, _vp, _u32, _u32, _u32, _vp, _vp, _vp, _vp, _sz, _vp],
     "hc_search_batch_noalloc": [_vp, _vp, _u32, _u32, _u32, _vp, _vp, _vp, _vp],
     "hc_encode_queries": [_vp, _vp, _u32, _vp, _sz, _vp],

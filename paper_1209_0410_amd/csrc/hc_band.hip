@@ -43,18 +43,32 @@ struct BandArgs {
     uint32_t *counts;     // [curves][nbuckets] -> scanned -> cursors
     uint32_t nbuckets;
     uint32_t *order;      // [curves][nq]
-    uint64_t *partial;    // [q][curves][k]
+    uint64_t *partial;    // [q][curves][k] (k > 16, first pass: [q][curves][2 kBandK])
     uint32_t *bound;      // [q]: least k-th distance of the curves done so far
     uint32_t *out_ids, *out_dists;
+    // k > 16 (two passes): the threshold key of each query, the number of
+    // pairs at or below it collected in buf ([q][cap]), and the queries left
+    // to the gather kernel
+    uint64_t *theta;
+    uint32_t *cnt;
+    uint64_t *buf;
+    uint32_t cap;
+    uint32_t *redo;
 };
 
+constexpr uint32_t kBandCap = 1024;   // k > 16: pairs collected per query (buffer entries)
+
 struct BandLayout {
-    size_t qkeys, pos, counts, order, partial, bound, total;
+    size_t qkeys, pos, counts, order, partial, bound, theta, cnt, redo, buf, total;
     uint32_t nbuckets;
 };
 
-inline BandLayout band_layout(uint32_t curves, uint64_t n, uint32_t nq)
+// k_max > 16 adds the two-pass buffers: 2 * kBandK first-pass entries per
+// query and curve, the threshold, the counters and kBandCap collected pairs
+// per query (8 KiB).
+inline BandLayout band_layout(uint32_t curves, uint64_t n, uint32_t nq, uint32_t k_max)
 {
+    const bool two = k_max > (uint32_t)kBandK;
     BandLayout L{};
     L.nbuckets = (uint32_t)((n >> kBucketShift) + 1);
     size_t off = 0;
@@ -67,9 +81,20 @@ inline BandLayout band_layout(uint32_t curves, uint64_t n, uint32_t nq)
     L.order = off;
     off = align256(off + sizeof(uint32_t) * (size_t)curves * nq);
     L.partial = off;
-    off = align256(off + sizeof(uint64_t) * (size_t)nq * curves * kBandK);
+    off = align256(off + sizeof(uint64_t) * (size_t)nq * curves * (two ? 2 * kBandK : kBandK));
     L.bound = off;
     off = align256(off + sizeof(uint32_t) * (size_t)nq);
+    L.theta = L.cnt = L.redo = L.buf = 0;
+    if (two) {
+        L.theta = off;
+        off = align256(off + sizeof(uint64_t) * (size_t)nq);
+        L.cnt = off;
+        off = align256(off + sizeof(uint32_t) * (size_t)nq);
+        L.redo = off;
+        off = align256(off + sizeof(uint32_t) * (size_t)nq);
+        L.buf = off;
+        off = align256(off + sizeof(uint64_t) * (size_t)nq * kBandCap);
+    }
     L.total = off;
     return L;
 }
@@ -525,7 +550,17 @@ __device__ inline void unroll_blocks(F &f)
     }
 }
 
-template <int KR, int NW>
+// Modes of the row-store kernel:
+//  kBandLists:  every query keeps its k (<= 16) nearest of the curve's window,
+//               with the bound shared between curves (the search for k <= 16);
+//  kBandHalves: every lane keeps the 16 nearest of its half of the rows and
+//               both halves are written out, no bound shared (first pass for
+//               k > 16: 32 candidates per curve, the source of the threshold);
+//  kBandThresh: every pair of the window at or below the query's threshold
+//               key is appended to the query's buffer (second pass for k > 16).
+constexpr int kBandLists = 0, kBandHalves = 1, kBandThresh = 2;
+
+template <int KR, int NW, int MODE>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(KR > 10 ? 3 : 4)))
 void k_band_dma(BandArgs a)
 {
@@ -605,13 +640,20 @@ void k_band_dma(BandArgs a)
     // bound from the other curves in the sum's terms; later reads come by
     // DMA into bslot every 8 tiles
     int ext = INT32_MAX;
-    {
+    uint64_t theta = kNone;     // kBandThresh: the query's threshold key
+    if (MODE == kBandLists) {
         const uint32_t b = live ? __hip_atomic_load(a.bound + q, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT)
                                 : kEmpty;
         if (b != kEmpty) ext = (int)b - cq;
         // taken now, before any copy is in flight (waiting for it later would
         // wait for the copies too)
+        asm volatile("" : "+v"(ext)::"memory");
+    } else if (MODE == kBandThresh) {
+        // no threshold (fewer than k distinct candidates in the first pass):
+        // nothing is collected and the gather kernel answers the query
+        theta = live ? a.theta[q] : kNone;
+        ext = theta == kNone ? INT32_MIN : (int)(uint32_t)(theta >> 32) - cq;
         asm volatile("" : "+v"(ext)::"memory");
     }
 
@@ -669,12 +711,14 @@ void k_band_dma(BandArgs a)
             const uint32_t crow_l = lds_addr(&S.crow2[0]) + 16 * h;
             const uint32_t rid_l = lds_addr(&S.rid[0]), par_l = lds_addr(&S.par[0]);
 
-            const int own = list_bound(L, cq);
-            int th = own;
-            {
+            int th = ext;
+            if (MODE == kBandLists) {
+                const int own = list_bound(L, cq);
                 const int other = __shfl_xor(own, 32, 64);
+                th = own < th ? own : th;
                 th = other < th ? other : th;
-                th = ext < th ? ext : th;
+            } else if (MODE == kBandHalves) {
+                th = list_bound(L, cq);
             }
             const uint32_t rlo = lo > t0 ? std::min<uint32_t>(lo - t0, R) : 0u;
             const uint32_t rhi = hi > t0 ? std::min<uint32_t>(hi - t0, R) : 0u;
@@ -687,7 +731,12 @@ void k_band_dma(BandArgs a)
                 asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(p), "+v"(id));
                 const int t = 2 * pend_h + (int)p;
                 const uint64_t key = ((uint64_t)(uint32_t)(t + cq) << 32) | id;
-                if (key < L[KR - 1]) {
+                if (MODE == kBandThresh) {
+                    if (key <= theta) {
+                        const uint32_t at = atomicAdd(a.cnt + q, 1u);
+                        if (at < a.cap) a.buf[(uint64_t)q * a.cap + at] = key;
+                    }
+                } else if (key < L[KR - 1]) {
 #pragma unroll
                     for (int m = KR - 1; m > 0; m--)
                         L[m] = key < L[m - 1] ? L[m - 1] : (key < L[m] ? key : L[m]);
@@ -769,7 +818,7 @@ void k_band_dma(BandArgs a)
     for (uint32_t g = 0; g < NG; g++) {
         __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0)
         __builtin_amdgcn_s_barrier();
-        if (g >= 1 && ((g - 1) & 3) == 3) {
+        if (MODE == kBandLists && g >= 1 && ((g - 1) & 3) == 3) {
             uint32_t b = lds_b32(lds_addr(&bslot[wv][qn]));
             asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(b));
             if (live && b != kEmpty) {
@@ -778,7 +827,8 @@ void k_band_dma(BandArgs a)
             }
         }
         if (g + 1 < NG) {
-            if ((g & 3) == 3 && lane < kMQ) dma4(a.bound + q, &bslot[wv][0]);
+            if (MODE == kBandLists && (g & 3) == 3 && lane < kMQ)
+                dma4(a.bound + q, &bslot[wv][0]);
             asm volatile("" ::: "memory");
             issue_group(g + 1);
         }
@@ -789,6 +839,16 @@ void k_band_dma(BandArgs a)
         }
     }
 
+    if (MODE == kBandThresh) return;
+    if (MODE == kBandHalves) {
+        // both halves' lists: entries [16 h, 16 h + 16) of the query's 32 for curve c
+        if (live) {
+            uint64_t *out = a.partial + ((uint64_t)q * C + c) * (2 * kBandK) + kBandK * h;
+#pragma unroll
+            for (int i = 0; i < KR; i++) out[i] = L[i];
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < KR; i++) {
         const uint64_t o = shfl_xor_u64(L[i], 32);
@@ -852,6 +912,63 @@ __global__ __launch_bounds__(64 * kMergeWaves) void k_band_merge(BandArgs a)
             head = hc < k ? ls[lane * k + hc] : kNone;
         }
     }
+}
+
+// k > 16, between the passes: one wavefront per query takes the k nearest
+// distinct keys among the first pass's 32 C candidates (all members of the
+// query's union), and the k-th of them is the threshold: the union's k
+// nearest are all at or below it.  Fewer than k distinct candidates leave no
+// threshold (kNone).  Clears the query's counter and fallback flag.
+__global__ __launch_bounds__(64) void k_band_theta(BandArgs a)
+{
+    __shared__ TopKShared sh;
+    const int lane = threadIdx.x;
+    const uint32_t q = blockIdx.x;
+    const uint32_t m = a.v.curves * 2 * kBandK;
+    const uint64_t *src = a.partial + (uint64_t)q * m;
+    WaveTopK<0> tk;
+    tk.init(a.k, &sh, lane);
+    for (uint32_t i0 = 0; i0 < m; i0 += 64) {
+        const uint32_t i = i0 + (uint32_t)lane;
+        tk.push(i < m ? src[i] : kNone, lane);
+    }
+    tk.finish(lane, [&](uint32_t j, uint64_t key) {
+        if (j == a.k - 1) a.theta[q] = key;
+    });
+    if (lane == 0) {
+        a.cnt[q] = 0;
+        a.redo[q] = 0;
+    }
+}
+
+// k > 16, after the second pass: one wavefront per query keeps the k nearest
+// distinct keys of the pairs collected at or below the threshold (a key met
+// in several curves' windows is taken once).  They are the query's result:
+// every member of the union at or below the threshold was collected, and the
+// union's k nearest are among them.  A query without a threshold or whose
+// pairs overflowed the buffer is flagged for the gather kernel.
+__global__ __launch_bounds__(64) void k_band_select(BandArgs a)
+{
+    __shared__ TopKShared sh;
+    const int lane = threadIdx.x;
+    const uint32_t q = blockIdx.x;
+    const uint32_t cnt = a.cnt[q];
+    if (a.theta[q] == kNone || cnt > a.cap) {        // the whole wavefront
+        if (lane == 0) a.redo[q] = 1;
+        return;
+    }
+    const uint64_t *src = a.buf + (uint64_t)q * a.cap;
+    WaveTopK<0> tk;
+    tk.init(a.k, &sh, lane);
+    for (uint32_t i0 = 0; i0 < cnt; i0 += 64) {
+        const uint32_t i = i0 + (uint32_t)lane;
+        tk.push(i < cnt ? src[i] : kNone, lane);
+    }
+    const uint64_t o = (uint64_t)q * a.k;
+    tk.finish(lane, [&](uint32_t j, uint64_t key) {
+        a.out_ids[o + j] = (uint32_t)key;
+        a.out_dists[o + j] = (uint32_t)(key >> 32);
+    });
 }
 
 // Row store of curve c: 8 lanes per list entry, each 16 bytes of the row
@@ -919,9 +1036,9 @@ static RowStoreLayout rowstore_layout(uint32_t curves, uint64_t n)
     return L;
 }
 
-size_t band_scratch_bytes(uint32_t curves, uint64_t n, uint32_t nq)
+size_t band_scratch_bytes(uint32_t curves, uint64_t n, uint32_t nq, uint32_t k_max)
 {
-    return band_layout(curves, n, nq).total;
+    return band_layout(curves, n, nq, k_max).total;
 }
 
 template <int NW>
@@ -931,16 +1048,32 @@ static void launch_band(const IndexView &v, uint32_t k, uint32_t nq, const BandA
     const uint32_t blocks = (uint32_t)(((uint64_t)nq + NW * kMQ - 1) / (NW * kMQ)) * v.curves;
     const dim3 grid(blocks), block(64 * NW);
     if (v.rows[0]) {
-        if (k == 1) hipLaunchKernelGGL((k_band_dma<1, NW>), grid, block, 0, st, a);
-        else if (k <= 4) hipLaunchKernelGGL((k_band_dma<4, NW>), grid, block, 0, st, a);
-        else if (k <= 10) hipLaunchKernelGGL((k_band_dma<10, NW>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_band_dma<kBandK, NW>), grid, block, 0, st, a);
+        if (k == 1) hipLaunchKernelGGL((k_band_dma<1, NW, kBandLists>), grid, block, 0, st, a);
+        else if (k <= 4)
+            hipLaunchKernelGGL((k_band_dma<4, NW, kBandLists>), grid, block, 0, st, a);
+        else if (k <= 10)
+            hipLaunchKernelGGL((k_band_dma<10, NW, kBandLists>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_band_dma<kBandK, NW, kBandLists>), grid, block, 0, st, a);
     } else {
         if (k == 1) hipLaunchKernelGGL((k_band<1, NW>), grid, block, 0, st, a);
         else if (k <= 4) hipLaunchKernelGGL((k_band<4, NW>), grid, block, 0, st, a);
         else if (k <= 10) hipLaunchKernelGGL((k_band<10, NW>), grid, block, 0, st, a);
         else hipLaunchKernelGGL((k_band<kBandK, NW>), grid, block, 0, st, a);
     }
+}
+
+// The two passes of k > 16 (row store only): 16 nearest per lane half, then
+// every pair at or below the threshold.
+template <int NW>
+static void launch_band_two(const IndexView &v, uint32_t nq, const BandArgs &a, int mode,
+                            hipStream_t st)
+{
+    const uint32_t blocks = (uint32_t)(((uint64_t)nq + NW * kMQ - 1) / (NW * kMQ)) * v.curves;
+    const dim3 grid(blocks), block(64 * NW);
+    if (mode == kBandHalves)
+        hipLaunchKernelGGL((k_band_dma<kBandK, NW, kBandHalves>), grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL((k_band_dma<1, NW, kBandThresh>), grid, block, 0, st, a);
 }
 
 uint64_t band_blocks(uint32_t curves, uint32_t nq, uint32_t w)
@@ -958,8 +1091,9 @@ hc_status band_search(const IndexView &v, const uint8_t *d_queries, uint32_t nq,
                       uint32_t *d_out_dists, void *d_scratch, size_t scratch_bytes,
                       hipStream_t st, hipEvent_t ev_begin, hipEvent_t ev_end)
 {
-    if (k < 1 || k > (uint32_t)kBandK) return HC_ERR_UNSUPPORTED;
-    const BandLayout L = band_layout(v.curves, v.n, nq);
+    const bool two = k > (uint32_t)kBandK;
+    if (k < 1 || k > kBandKMax || (two && !v.rows[0])) return HC_ERR_UNSUPPORTED;
+    const BandLayout L = band_layout(v.curves, v.n, nq, k);
     if (scratch_bytes < L.total) return HC_ERR_SIZE;
     uint8_t *s = (uint8_t *)d_scratch;
     BandArgs a;
@@ -979,6 +1113,13 @@ hc_status band_search(const IndexView &v, const uint8_t *d_queries, uint32_t nq,
     a.bound = (uint32_t *)(s + L.bound);
     a.out_ids = d_out_ids;
     a.out_dists = d_out_dists;
+    if (two) {
+        a.theta = (uint64_t *)(s + L.theta);
+        a.cnt = (uint32_t *)(s + L.cnt);
+        a.redo = (uint32_t *)(s + L.redo);
+        a.buf = (uint64_t *)(s + L.buf);
+        a.cap = kBandCap;
+    }
     const uint64_t nc = (uint64_t)v.curves * L.nbuckets;
     hipLaunchKernelGGL(k_band_fill, dim3((uint32_t)std::min<uint64_t>(4096, (nc + 255) / 256)),
                        dim3(256), 0, st, a.counts, nc, 0u);
@@ -992,6 +1133,22 @@ hc_status band_search(const IndexView &v, const uint8_t *d_queries, uint32_t nq,
     hipLaunchKernelGGL(k_band_scatter, dim3((uint32_t)((nt + 255) / 256)), dim3(256), 0, st, a);
     hc_status rs = record_if(ev_begin, st);
     if (rs != HC_OK) return rs;
+    if (two) {
+        // first pass, threshold, second pass; then the selection and, for
+        // the queries it flags, the gather kernel
+        if (w_fixed < kBandWideW) launch_band_two<4>(v, nq, a, kBandHalves, st);
+        else launch_band_two<8>(v, nq, a, kBandHalves, st);
+        hipLaunchKernelGGL(k_band_theta, dim3(nq), dim3(64), 0, st, a);
+        if (w_fixed < kBandWideW) launch_band_two<4>(v, nq, a, kBandThresh, st);
+        else launch_band_two<8>(v, nq, a, kBandThresh, st);
+        rs = record_if(ev_end, st);
+        if (rs != HC_OK) return rs;
+        hipLaunchKernelGGL(k_band_select, dim3(nq), dim3(64), 0, st, a);
+        rs = last_hip();
+        if (rs != HC_OK) return rs;
+        return gather_search_only(v, d_queries, a.qkeys, nq, k, w_fixed, d_w, a.redo,
+                                  d_out_ids, d_out_dists, st);
+    }
     if (w_fixed < kBandWideW) launch_band<4>(v, k, nq, a, st);
     else launch_band<8>(v, k, nq, a, st);
     rs = record_if(ev_end, st);

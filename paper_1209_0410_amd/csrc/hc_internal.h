@@ -112,8 +112,17 @@ inline hc_status record_if(hipEvent_t ev, hipStream_t st)
 hc_status encode_rows(const IndexView &v, const uint8_t *rows, uint64_t nrows, Key *keys,
                       hipStream_t s);
 
+// Gather search (hc_search.hip) of the queries q with only[q] != 0, keys in qkeys.
+hc_status gather_search_only(const IndexView &v, const uint8_t *d_queries, const Key *qkeys,
+                             uint32_t nq, uint32_t k, uint32_t w_fixed, const uint32_t *d_w,
+                             const uint32_t *only, uint32_t *d_out_ids, uint32_t *d_out_dists,
+                             hipStream_t st);
+
 // Banded search (hc_band.hip), query keys already at the start of d_scratch.
-size_t band_scratch_bytes(uint32_t curves, uint64_t n, uint32_t nq);
+// Scratch for a batch of nq queries with k up to k_max (k_max > 16 adds the
+// buffers of the two-pass search; it needs the row store).
+size_t band_scratch_bytes(uint32_t curves, uint64_t n, uint32_t nq, uint32_t k_max);
+constexpr uint32_t kBandKMax = HC_BAND_K_MAX;   // largest k the banded path takes
 uint64_t band_blocks(uint32_t curves, uint32_t nq, uint32_t w);   // blocks of its main kernel
 hc_status band_search(const IndexView &v, const uint8_t *d_queries, uint32_t nq, uint32_t k,
                       uint32_t w_fixed, const uint32_t *d_w, uint32_t *d_out_ids,

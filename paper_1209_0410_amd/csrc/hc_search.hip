@@ -33,6 +33,7 @@
 namespace hc {
 
 constexpr int kKR = 16;                 // longest register list (k <= 16)
+constexpr uint32_t kBandK16 = 16;       // k the banded path takes in one pass
 constexpr double kBandShare = 3.5;      // windows per list entry from which to band
 constexpr double kBandMinBlocks = 512;  // banded blocks from which to band (2 per CU)
                                         // (MI355X, n = 1e7, nq = 1e5: break-even at w ~ 512)
@@ -51,6 +52,7 @@ struct SearchArgs {
     uint32_t *out_cand;
     uint32_t cand_stride;
     uint32_t cs_log2;          // set kernel: union capacity = 1 << cs_log2
+    const uint32_t *only;      // search: when set, only queries q with only[q] != 0
 };
 
 // ---------------------------------------------------------------------------
@@ -73,6 +75,7 @@ void k_stream(SearchArgs a)
     const int lane = threadIdx.x;
     const uint32_t q = blockIdx.x;
     if (q >= a.nq) return;
+    if (a.only && !a.only[q]) return;          // the whole block
     uint4 qv;
     uint32_t qq;
     query_part(a.queries, q, lane, qv, qq);
@@ -247,6 +250,28 @@ static hc_status launch_sets(const SearchArgs &a, hipStream_t st)
     return last_hip();
 }
 
+// The gather search for the queries q with only[q] != 0 of a batch whose keys
+// are already in qkeys (the banded path's fallback for k > 16).
+hc_status gather_search_only(const IndexView &v, const uint8_t *d_queries, const Key *qkeys,
+                             uint32_t nq, uint32_t k, uint32_t w_fixed, const uint32_t *d_w,
+                             const uint32_t *only, uint32_t *d_out_ids, uint32_t *d_out_dists,
+                             hipStream_t st)
+{
+    SearchArgs a;
+    memset(&a, 0, sizeof(a));
+    a.v = v;
+    a.queries = d_queries;
+    a.qkeys = qkeys;
+    a.nq = nq;
+    a.k = k;
+    a.w_fixed = w_fixed;
+    a.d_w = d_w;
+    a.out_ids = d_out_ids;
+    a.out_dists = d_out_dists;
+    a.only = only;
+    return launch_search(a, w_fixed, st);
+}
+
 static hc_status check_common(const hc_index *idx, const uint8_t *d_queries, void *d_scratch,
                               size_t scratch_bytes, uint32_t nq)
 {
@@ -303,10 +328,17 @@ extern "C" {
 
 hc_status hc_search_scratch_bytes(const hc_index *idx, uint32_t nq, size_t *bytes)
 {
-    if (!idx || !bytes) return HC_ERR_INVALID;
+    return hc_search_scratch_bytes_k(idx, nq, (uint32_t)kBandK16, bytes);
+}
+
+hc_status hc_search_scratch_bytes_k(const hc_index *idx, uint32_t nq, uint32_t k_max,
+                                    size_t *bytes)
+{
+    if (!idx || !bytes || k_max < 1 || k_max > HC_K_MAX) return HC_ERR_INVALID;
     const uint32_t m = std::max<uint32_t>(nq, 1);
+    const uint32_t kb = std::min<uint32_t>(k_max, kBandKMax);
     *bytes = std::max(align256(sizeof(Key) * (size_t)m * idx->v.curves),
-                      band_scratch_bytes(idx->v.curves, idx->v.n, m));
+                      band_scratch_bytes(idx->v.curves, idx->v.n, m, kb));
     return HC_OK;
 }
 
@@ -366,8 +398,10 @@ hc_status hc_search_choose_path(const hc_index *idx, uint32_t nq, uint32_t k, ui
     // block over a long stretch of the list, streamed by few blocks)
     const bool shared = 2.0 * (double)w * nq >= kBandShare * (double)idx->v.n;
     const bool wide = (double)band_blocks(idx->v.curves, nq, w) >= kBandMinBlocks;
-    const bool fits = scratch_bytes >= band_scratch_bytes(idx->v.curves, idx->v.n, nq);
-    *path = (shared && wide && fits && k >= 1 && k <= 16) ? HC_PATH_BAND : HC_PATH_GATHER;
+    // k <= 16: one pass; 16 < k <= kBandKMax: two passes over the row store
+    const bool k_ok = k >= 1 && (k <= kBandK16 || (k <= kBandKMax && idx->v.rows[0]));
+    const bool fits = k_ok && scratch_bytes >= band_scratch_bytes(idx->v.curves, idx->v.n, nq, k);
+    *path = (shared && wide && fits) ? HC_PATH_BAND : HC_PATH_GATHER;
     return HC_OK;
 }
 

@@ -137,9 +137,11 @@ class Index:
             self.handle = None
 
     # -- helpers --------------------------------------------------------------
-    def scratch(self, nq):
+    def scratch(self, nq, k_max=16):
+        """The index's shared scratch, grown to hold a batch of nq queries with
+        k up to k_max on either path (hc_search_scratch_bytes_k)."""
         sz = ct.c_size_t()
-        capi.call("hc_search_scratch_bytes", self.handle, nq, ct.byref(sz))
+        capi.call("hc_search_scratch_bytes_k", self.handle, nq, int(k_max), ct.byref(sz))
         if self._scratch is None or self._scratch.numel() < sz.value:
             self._scratch = _empty_bytes(sz.value, self.db.device)
         return self._scratch
@@ -147,16 +149,16 @@ class Index:
     def path(self, nq, k, w, scratch_bytes=None):
         """Execution path hc_search_encoded takes (capi.HC_PATH_GATHER / _BAND)."""
         if scratch_bytes is None:
-            scratch_bytes = self.scratch(nq).numel()
+            scratch_bytes = self.scratch(nq, k).numel()
         p = ct.c_uint32()
         capi.call("hc_search_choose_path", self.handle, nq, k, int(w), scratch_bytes,
                   ct.byref(p))
         return p.value
 
-    def new_scratch(self, nq):
+    def new_scratch(self, nq, k_max=16):
         """A scratch buffer of its own (for concurrent streams)."""
         sz = ct.c_size_t()
-        capi.call("hc_search_scratch_bytes", self.handle, nq, ct.byref(sz))
+        capi.call("hc_search_scratch_bytes_k", self.handle, nq, int(k_max), ct.byref(sz))
         return _empty_bytes(sz.value, self.db.device)
 
     def curve(self, c):
@@ -180,7 +182,7 @@ class Index:
             dists = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
         else:
             ids, dists = out
-        sc = scratch if scratch is not None else self.scratch(nq)
+        sc = scratch if scratch is not None else self.scratch(nq, k)
         wp = None
         if w_per_query is not None:
             assert w_per_query.dtype == torch.int32 and w_per_query.is_cuda

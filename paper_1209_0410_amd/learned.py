@@ -231,10 +231,12 @@ def recall_at_k(ids, truth):
 
 def quick_path(ix: Index, nq, k, w):
     """The faster execution path for a calibration batch: banded when each list
-    entry lies in several of the batch's windows (k <= 16), whatever the block
+    entry lies in several of the batch's windows (k <= 16, or up to
+    HC_BAND_K_MAX with the row store attached), whatever the block
     count (both paths give the same results; the automatic choice also wants
     enough blocks to fill the device, which a small batch lacks)."""
-    return capi.HC_PATH_BAND if (k <= 16 and 2.0 * w * nq >= 3.5 * ix.n) else capi.HC_PATH_GATHER
+    band_k = k <= 16 or (k <= capi.HC_BAND_K_MAX and getattr(ix, "rowstore", None) is not None)
+    return capi.HC_PATH_BAND if (band_k and 2.0 * w * nq >= 3.5 * ix.n) else capi.HC_PATH_GATHER
 
 
 def calibrate_delta(ix: Index, model: WModel, queries, feats, truth, k, target=0.90,

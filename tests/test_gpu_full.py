@@ -73,6 +73,29 @@ def test_full_size_sampled_rows_bit_exact(full, w, path, k):
     assert (ids < N).all()
 
 
+@pytest.mark.parametrize("k", [17, 100])
+def test_full_size_band_two_pass_sampled_rows_bit_exact(full, k):
+    """k > 16 on the banded path at full size (two passes over the row store,
+    the scratch sized for that k), launched as the timed step is."""
+    import torch
+    gix = full["gix"]
+    sc = gix.new_scratch(Q, k)
+    out = tuple(torch.empty((Q, k), dtype=torch.int32, device=full["gq"].device)
+                for _ in range(2))
+    assert gix.path(Q, k, W_RECALL90, sc.numel()) == PATH_BAND
+    print(f"[full] k={k} banded two passes on {len(full['pick'])} sampled queries", flush=True)
+    gix.encode_queries(full["gq"], sc)
+    gix.search_encoded(full["gq"], k, W_RECALL90, out, sc)
+    ids, d = u32(out[0]), u32(out[1])
+    del sc
+    pick = full["pick"]
+    rid, rd = full["oix"].search(full["q"][pick], k, W_RECALL90)
+    assert (ids[pick] == rid).all() and (d[pick] == rd).all()
+    key = (d.astype(np.uint64) << np.uint64(32)) | ids.astype(np.uint64)
+    assert (key[:, 1:] > key[:, :-1]).all()
+    assert (ids < N).all()
+
+
 def test_full_size_per_query_w_sampled_rows_bit_exact(full):
     """The learned step's launch: a w per query (here log-uniform over the
     spread the learned model gives at recall 0.90) on the banded path."""
