@@ -86,6 +86,9 @@ def parse():
     ap.add_argument("--cpu-seconds-1t", type=float, default=6.0)
     ap.add_argument("--probe-gib", type=int, default=8,
                     help="GiB read by the streaming-read probe (0 = skip)")
+    ap.add_argument("--power-seconds", type=float, default=5.0,
+                    help="repeat the headline step this long while sampling power and clock "
+                         "(0 = skip)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also copy 1 GiB device-to-device 3 times (counter calibration)")
     return ap.parse_args()
@@ -299,13 +302,16 @@ def main():
         rowstore_bytes = ix.attach_rowstore()
         torch.cuda.synchronize()
         log(f"row store {rowstore_bytes / 1e9:.2f} GB")
-    sc = ix.scratch(a.nq)
+    sc = ix.scratch(a.nq, a.k)
     out = (torch.empty((a.nq, k), dtype=torch.int32, device=dev),
            torch.empty((a.nq, k), dtype=torch.int32, device=dev))
 
     # exact kNN truth for every evaluation query; the oracle checks a sample
     t0 = time.time()
-    tid, _ = brute_force(gdb, gq, k)
+    # recall@10 (of the first min(k, 10) results for k below 10): the exact
+    # kNN truth is taken to that depth
+    kt = min(k, 10)
+    tid, _ = brute_force(gdb, gq, kt)
     truth = u32(tid)
     log(f"exact kNN of {a.nq} evaluation queries in {time.time() - t0:.1f}s")
 
@@ -318,7 +324,7 @@ def main():
     # ---- fixed w at recall >= 0.90 ----------------------------------------
     cq = datagen.make_queries(a.calib_q, seed=datagen.SEED_CALIB)
     gcq = torch.from_numpy(cq).to(dev)
-    ctruth, _ = brute_force(gdb, gcq, k)
+    ctruth, _ = brute_force(gdb, gcq, kt)
     t0 = time.time()
     if a.w_fixed:
         w_fix, rec_c = a.w_fixed, None
@@ -340,7 +346,9 @@ def main():
 
     # ---- learned w ----------------------------------------------------------
     learned_row, model, learned_out, wq = None, None, None, None
-    if a.train > 0:
+    if a.train > 0 and k > 16:
+        log("learned w skipped: its labels take the exact top-k, k <= 16")
+    elif a.train > 0:
         learned_row, model, learned_out, wq = run_learned(a, ix, rank, gdb, gq, gcq, ctruth,
                                                           out, sc, recall_of, work, stream, dev)
 
@@ -360,6 +368,16 @@ def main():
     log(f"{lat['batch']}-query sub-batches: p50 {lat['p50']:.3f} ms, p99 {lat['p99']:.3f} ms")
 
     # ---- the device's streaming-read bandwidth ------------------------------
+    # ---- power and clock under the headline step ----------------------------
+    power = power_leg(a, learned_step(ix, model, gq, k, out, sc,
+                                      torch.empty((a.nq, 24), dtype=torch.float32, device=dev),
+                                      torch.empty(a.nq, dtype=torch.int32, device=dev))
+                      if use_learned else fixed_step(ix, gq, k, w_fix, out, sc, forced),
+                      stream)
+    if power:
+        log(f"power: {power['socket_power_W']:.0f} W, GFX clock {power['gfx_clock_MHz']:.0f} MHz "
+            f"over {power['steps']} steps ({power['samples']} samples)")
+
     probe = read_probe(a, dev) if a.probe_gib else None
     if probe:
         log(f"streaming read: {probe['GBs']:.0f} GB/s ({probe['bytes'] / 2**30:.0f} GiB, "
@@ -368,7 +386,7 @@ def main():
     # ---- the GPU truth against the oracle; the oracle's own timing -----------
     cpu, check = None, None
     if a.cpu_baseline:
-        check, cpu = oracle_legs(a, db[:a.n], q, truth, k, w_fix, fixed_out, learned_out,
+        check, cpu = oracle_legs(a, db[:a.n], q, truth, kt, k, w_fix, fixed_out, learned_out,
                                  None if wq is None else u32(wq), use_learned, ix, rank, gq,
                                  dev)
 
@@ -414,6 +432,7 @@ def main():
         "end_to_end": e2e,
         "latency_ms": lat,
         "read_probe": probe,
+        "power": power,
         "build_s": build_s,
         "truth_check": check,
         "secondary": secondary,
@@ -559,6 +578,60 @@ def sub_batch_latency(a, ix, model, gq, k, w_fix, out, sc, stream):
             "p99": float(np.percentile(ms, 99))}
 
 
+def power_leg(a, fn, stream):
+    """Socket power and GFX clock while the headline step repeats for
+    --power-seconds: amd-smi sampled from a thread (about 3 samples/s),
+    samples in the middle of the loop only.  None without amd-smi."""
+    import shutil
+    import subprocess
+    import threading
+    import torch
+    smi = shutil.which("amd-smi")
+    if not smi or a.power_seconds <= 0:
+        return None
+    samples, stop = [], threading.Event()
+
+    def sampler():
+        while not stop.is_set():
+            t = time.time()
+            try:
+                r = subprocess.run([smi, "metric", "-g", "0", "-c", "-p", "--json"],
+                                   capture_output=True, text=True, timeout=10)
+                d = json.loads(r.stdout)["gpu_data"][0]
+                clk = [v["clk"]["value"] for key, v in d["clock"].items()
+                       if key.startswith("gfx_") and isinstance(v, dict)
+                       and isinstance(v.get("clk"), dict)]
+                samples.append((t, float(d["power"]["socket_power"]["value"]),
+                                float(np.mean(clk))))
+            except Exception:
+                pass
+            stop.wait(0.2)
+
+    for _ in range(2):
+        fn(None, stream)
+    torch.cuda.synchronize()
+    th = threading.Thread(target=sampler, daemon=True)
+    th.start()
+    t0 = time.time()
+    steps = 0
+    while time.time() - t0 < a.power_seconds:
+        for _ in range(5):
+            fn(None, stream)
+        torch.cuda.synchronize()
+        steps += 5
+    t1 = time.time()
+    stop.set()
+    th.join()
+    mid = [s for s in samples if t0 + 0.5 <= s[0] <= t1 - 0.3]
+    if not mid:
+        return None
+    return {"seconds": t1 - t0, "steps": steps, "ms_per_step": (t1 - t0) / steps * 1e3,
+            "samples": len(mid), "socket_power_W": float(np.mean([s[1] for s in mid])),
+            "socket_power_W_max": max(s[1] for s in mid),
+            "gfx_clock_MHz": float(np.mean([s[2] for s in mid])),
+            "gfx_clock_MHz_min": min(s[2] for s in mid)}
+
+
 def read_probe(a, dev):
     """Achievable streaming-read bandwidth: hc_read_probe over a buffer of
     --probe-gib GiB, median of 5 runs after one warm-up."""
@@ -603,8 +676,8 @@ def cpu_model():
     return None
 
 
-def oracle_legs(a, db, q, truth, k, w_fix, fixed_out, learned_out, wv, use_learned, ix, rank,
-                gq, dev):
+def oracle_legs(a, db, q, truth, kt, k, w_fix, fixed_out, learned_out, wv, use_learned, ix,
+                rank, gq, dev):
     """(1) The GPU exact kNN against the oracle's on the first --truth-check
     evaluation queries and on 64 training queries, and the GPU labels of those
     training queries against the oracle's.  (2) The oracle's search timed on
@@ -617,7 +690,7 @@ def oracle_legs(a, db, q, truth, k, w_fix, fixed_out, learned_out, wv, use_learn
     from paper_1209_0410_amd.index import brute_force
     m = min(a.truth_check, q.shape[0])
     t0 = time.time()
-    rid, _ = oracle.brute_force(db, q[:m], k)
+    rid, _ = oracle.brute_force(db, q[:m], kt)
     if not (rid == truth[:m]).all():
         raise AssertionError("GPU exact kNN differs from the oracle on evaluation queries")
     log(f"GPU exact kNN equals the oracle's on {m} evaluation queries "
@@ -627,7 +700,7 @@ def oracle_legs(a, db, q, truth, k, w_fix, fixed_out, learned_out, wv, use_learn
     build = time.time() - t0
     log(f"oracle index over {db.shape[0]} rows built in {build:.1f}s")
     check = {"eval_queries": m}
-    if a.train:
+    if a.train and k <= 16:
         mt = 64
         tq = datagen.make_queries(mt, seed=datagen.SEED_TRAIN)
         gtq = torch.from_numpy(tq).to(dev)
@@ -706,15 +779,16 @@ def run_secondary(a, gdb_all, db, k, dev, stream):
     nq = 100_000
     q = datagen.make_queries(nq)                   # the plain-method batch (seed 2)
     gq = torch.from_numpy(q).to(dev)
-    sc = ix.scratch(nq)
+    sc = ix.scratch(nq, k)
     out = (torch.empty((nq, k), dtype=torch.int32, device=dev),
            torch.empty((nq, k), dtype=torch.int32, device=dev))
     rq = 10_000
-    truth = u32(brute_force(gdb, gq[:rq].contiguous(), k)[0])
+    kt = min(k, 10)
+    truth = u32(brute_force(gdb, gq[:rq].contiguous(), kt)[0])
     if a.cpu_baseline:
         import oracle
         m = min(a.truth_check, rq)
-        rid, _ = oracle.brute_force(db[:n2], q[:m], k)
+        rid, _ = oracle.brute_force(db[:n2], q[:m], kt)
         if not (rid == truth[:m]).all():
             raise AssertionError("GPU exact kNN differs from the oracle (secondary)")
         log(f"N={n2}: GPU exact kNN equals the oracle's on {m} queries")
@@ -737,7 +811,7 @@ def run_secondary(a, gdb_all, db, k, dev, stream):
             f"{roof['achieved']:.0f} {roof['unit']} ({roof['frac']:.1%} of {roof['bound']})")
     cq = datagen.make_queries(a.calib_q, seed=datagen.SEED_CALIB)
     gcq = torch.from_numpy(cq).to(dev)
-    ctruth, _ = brute_force(gdb, gcq, k)
+    ctruth, _ = brute_force(gdb, gcq, kt)
     w_c, rec_c = learned.calibrate_fixed_w(ix, gcq, ctruth, k, CALIB_TARGET, hi=1 << 17)
     t = summary(timed(fixed_step(ix, gq, k, w_c, out, sc, forced), a.steps, a.warmup, stream))
     p = path_name(forced if forced else ix.path(nq, k, w_c, sc.numel()))

@@ -75,7 +75,7 @@ class _Slot:
     (136 B per request); out, the ids then the distances, nq x k_stride each."""
     IN_BYTES = 136
 
-    def __init__(self, ix, cap, k_stride, dev, cfg):
+    def __init__(self, ix, cap, k_stride, dev, cfg, route="uneven"):
         self.stream = torch.cuda.Stream(device=dev)
         self.k_stride = k_stride
         self.d_in = torch.empty(cap * self.IN_BYTES, dtype=torch.uint8, device=dev)
@@ -84,8 +84,15 @@ class _Slot:
         self.feat = torch.empty((cap, learned.FEATURES), dtype=torch.float32, device=dev)
         self.d_out = torch.empty(2 * cap * k_stride, dtype=torch.int32, device=dev)
         self.h_out = torch.empty(2 * cap * k_stride, dtype=torch.int32).pin_memory()
-        self.scratch = ix.uneven_scratch(cap, k_stride, cfg)
         self.fscratch = ix.new_scratch(cap)
+        if route == "uneven":
+            self.scratch = ix.uneven_scratch(cap, k_stride, cfg)
+        else:
+            # one search per k class on the automatic path: the scratch of
+            # either path for k up to k_stride (banded two passes for k > 16)
+            self.scratch = ix.new_scratch(cap, k_stride)
+        self.classes = None          # batch route: (k, first, count) per class
+        self.perm = None             # batch route: packed position -> request
         self.done = torch.cuda.Event()
         self.busy = False
 
@@ -105,7 +112,8 @@ class _Slot:
 
 
 def batch_bytes(nq, k_stride, curves=8, max_split=32):
-    """Device bytes one batch of nq requests needs beyond the resident index."""
+    """Device bytes one batch of nq requests needs beyond the resident index
+    on the uneven route (input, features, w, outputs, item scratch)."""
     return nq * (128 + 8 + 4 * learned.FEATURES + 8 * k_stride +
                  16 * curves + 4 * curves + 4 + 8 * max_split * k_stride)
 
@@ -113,11 +121,23 @@ def batch_bytes(nq, k_stride, curves=8, max_split=32):
 class Server:
     """Admits arriving requests into batches on `slots` streams; with `host`
     (an index.HostSearch) and cpu_workers > 0, short queues go to host cores
-    (fixed w only: the learned w is inferred on the GPU)."""
+    (fixed w only: the learned w is inferred on the GPU).
+
+    route "uneven": one persistent launch per batch with per-request w and k
+    (hc_search_uneven; the gather kernel).  route "batch": the batch is packed
+    by k on the host and each k class is one hc_search_batch on the automatic
+    path, which bands large batches at large w (the row store attached; two
+    passes for k > 16) and gathers small ones.  A batch is formed when a slot
+    is free and at least min_batch requests wait, or the oldest has waited
+    max_wait_s, or no more will arrive."""
 
     def __init__(self, ix, model=None, w_fixed=64, k_stride=100, max_batch=4096, slots=3,
                  budget=None, cfg=None, w_fallback=None, host=None, cpu_workers=0,
-                 k_feature=10):
+                 k_feature=10, route="uneven", min_batch=1, max_wait_s=0.0):
+        if route not in ("uneven", "batch"):
+            raise ValueError(f"unknown route {route!r}")
+        if route == "batch" and host is not None:
+            raise ValueError("the cooperative scheduler uses the uneven route")
         if host is not None and model is not None:
             raise ValueError("the host path takes the fixed w; use model=None with host")
         self.ix = ix
@@ -130,11 +150,17 @@ class Server:
         self.k_stride = int(k_stride)
         self.max_batch = int(max_batch)
         self.cfg = cfg
+        self.route = route
+        self.min_batch = max(1, int(min_batch))
+        self.max_wait_s = float(max_wait_s)
         dev = ix.db.device
-        self.slots = [_Slot(ix, self.max_batch, self.k_stride, dev, cfg) for _ in range(slots)]
+        self.slots = [_Slot(ix, self.max_batch, self.k_stride, dev, cfg, route)
+                      for _ in range(slots)]
         self.budget = budget if budget is not None else HbmBudget()
 
     def _launch(self, slot, hq, hk, hkf, lo, hi):
+        if self.route == "batch":
+            return self._launch_batch(slot, hq, hk, hkf, lo, hi)
         nq = hi - lo
         # pack the batch on the host (rows, k, k'), then one copy in
         hin = slot.h_in[:nq * _Slot.IN_BYTES].numpy()
@@ -166,6 +192,72 @@ class Server:
             slot.h_out[:m].copy_(slot.d_out[:m], non_blocking=True)
             slot.done.record(slot.stream)
         slot.busy = True
+
+    def _bytes(self, nq):
+        """Device bytes charged to the budget for a batch of nq requests."""
+        if self.route == "uneven":
+            return batch_bytes(nq, self.k_stride)
+        # input, features, w and outputs; the search scratch is the slot's
+        return nq * (_Slot.IN_BYTES + 4 * learned.FEATURES + 4 + 8 * self.k_stride)
+
+    def _launch_batch(self, slot, hq, hk, hkf, lo, hi):
+        """The batch route: requests packed by k (stable), one copy in, the
+        learned w for all (if a model is given), one search per k class into
+        compact [count x k] blocks (all ids, then all distances), one copy out.
+        The host unpacks the blocks (_unpack)."""
+        nq = hi - lo
+        perm = np.argsort(hk[lo:hi], kind="stable")
+        kp = hk[lo:hi][perm]
+        classes, o = [], 0
+        for kv in np.unique(kp):
+            m = int(np.count_nonzero(kp == kv))
+            classes.append((int(kv), o, m))
+            o += m
+        hin = slot.h_in[:nq * _Slot.IN_BYTES].numpy()
+        hin[:nq * 128] = hq[lo:hi][perm].reshape(-1)
+        hin[nq * 128:nq * 132] = kp.view(np.uint8)
+        hin[nq * 132:nq * 136] = hkf[lo:hi][perm].view(np.uint8)
+        tot = sum(kv * m for kv, _, m in classes)
+        st = stream_of(slot.stream)
+        with torch.cuda.stream(slot.stream):
+            slot.d_in[:nq * _Slot.IN_BYTES].copy_(slot.h_in[:nq * _Slot.IN_BYTES],
+                                                   non_blocking=True)
+            q, _, kf = slot.inputs(nq)
+            if self.model is not None:
+                capi.call("hc_features", self.ix.handle, ctp(q), nq, int(self.k_stride),
+                          ctp(kf), ctp(slot.feat), ctp(slot.fscratch), slot.fscratch.numel(),
+                          st)
+                capi.call("hc_mlp_infer", ctp(self.model.bf16), ctp(self.model.norm),
+                          ctp(slot.feat), nq, float(self.model.delta), self.model.w_min,
+                          self.model.w_max, self.w_fallback, ctp(slot.w), None, st)
+            off = 0
+            for kv, first, m in classes:
+                qc = q[first:first + m]
+                ids = slot.d_out[off:off + m * kv]
+                dists = slot.d_out[tot + off:tot + off + m * kv]
+                # with a w per request, w_fixed is the typical w (sizes the work)
+                wp = ctp(slot.w[first:first + m]) if self.model is not None else None
+                wf = self.model.w_hint if self.model is not None else self.w_fixed
+                capi.call("hc_search_batch", self.ix.handle, ctp(qc), m, kv, int(wf), wp,
+                          ctp(ids), ctp(dists), ctp(slot.scratch), slot.scratch.numel(), st)
+                off += m * kv
+            slot.h_out[:2 * tot].copy_(slot.d_out[:2 * tot], non_blocking=True)
+            slot.done.record(slot.stream)
+        slot.classes, slot.perm, slot.tot = classes, perm, tot
+        slot.busy = True
+
+    def _unpack(self, slot, lo, hi, res_ids, res_d):
+        """Rows lo..hi-1 of the results from a finished batch-route slot: each
+        request's k results, then 0xFFFFFFFF up to k_stride."""
+        h = slot.h_out[:2 * slot.tot].numpy().view(np.uint32)
+        off = 0
+        for kv, first, m in slot.classes:
+            rows = lo + slot.perm[first:first + m]
+            res_ids[rows] = 0xFFFFFFFF
+            res_d[rows] = 0xFFFFFFFF
+            res_ids[rows, :kv] = h[off:off + m * kv].reshape(m, kv)
+            res_d[rows, :kv] = h[slot.tot + off:slot.tot + off + m * kv].reshape(m, kv)
+            off += m * kv
 
     def run(self, arrivals, queries, ks, keep_results=True, realtime=True, log=None):
         """Serves requests i (arrival time arrivals[i] s, row queries[i], k ks[i]).
@@ -220,7 +312,9 @@ class Server:
                 inflight.popleft()
                 t_done = clock() if realtime else 0.0
                 done_at[lo:hi] = t_done
-                if keep_results:
+                if keep_results and self.route == "batch":
+                    self._unpack(slot, lo, hi, res_ids, res_d)
+                elif keep_results:
                     hids, hd = slot.outputs(hi - lo, host=True)
                     res_ids[lo:hi] = hids.numpy().view(np.uint32)
                     res_d[lo:hi] = hd.numpy().view(np.uint32)
@@ -243,14 +337,18 @@ class Server:
                 nxt += take
                 on_cpu += take
             ready_end = min(arrived, nxt + self.max_batch)
+            # hold a small batch back while more requests are due soon
+            if (realtime and ready_end > nxt and ready_end - nxt < self.min_batch
+                    and arrived < R and now - arrivals[nxt] < self.max_wait_s):
+                ready_end = nxt
             if ready_end > nxt and free:
-                per = batch_bytes(1, self.k_stride)
+                per = self._bytes(1)
                 fit = (self.budget.budget - self.budget.used) // per
                 if fit < 1 and not inflight:
                     raise RuntimeError("HBM budget is below one request's device memory")
                 end = min(ready_end, nxt + int(fit))
-                if end > nxt and self.budget.take(batch_bytes(end - nxt, self.k_stride)):
-                    nb = batch_bytes(end - nxt, self.k_stride)
+                if end > nxt and self.budget.take(self._bytes(end - nxt)):
+                    nb = self._bytes(end - nxt)
                     self._launch(free[0], hq, hk, hkf, nxt, end)
                     inflight.append((free[0], nxt, end, nb))
                     sizes.append(end - nxt)
@@ -320,7 +418,15 @@ def main(argv=None):
     ap.add_argument("--slots", type=int, default=3)
     ap.add_argument("--max-batch", type=int, default=16_384)
     ap.add_argument("--recall-sample", type=int, default=2_000)
+    ap.add_argument("--recall", type=float, default=0.0,
+                    help="serve at this recall@10: calibrate the fixed w to it and take "
+                         "the batch route with the row store attached (0 = the "
+                         "equal-cost comparison of learned and fixed w)")
+    ap.add_argument("--min-batch", type=int, default=1)
+    ap.add_argument("--max-wait", type=float, default=0.0, help="seconds")
     a = ap.parse_args(argv)
+    if a.recall > 0:
+        return recall_main(a)
 
     def log(msg):
         print(f"[serve] {msg}", file=sys.stderr, flush=True)
@@ -399,6 +505,77 @@ def main(argv=None):
            "w_fixed": a.w, "w_max": a.w_max, "delta": model.delta,
            "mean_learned_w_sample": mean_w,
            "recall_at_min_k_10": rec, "recall_sample": S, **stats}
+    print(json.dumps(out), flush=True)
+
+
+def recall_main(a):
+    """The serving scenario at a recall target: the fixed w calibrated to
+    recall@10 >= target (plus a margin for sampling error) on 10^4
+    calibration queries, the row store attached, the batch route (large k
+    classes banded, small ones gathered).  Reports latency p50/p99, sustained
+    queries/s, the HBM held, recall@min(k, 10) of a sample of the served
+    requests, and that each of them equals its result searched alone."""
+    from . import datagen
+    from .index import Index, brute_force
+
+    def log(msg):
+        print(f"[serve] {msg}", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    db = datagen.make_db(a.n)
+    gdb = torch.from_numpy(db).to(dev)
+    del db
+    ix = Index(gdb)
+    rs = ix.attach_rowstore()
+    torch.cuda.synchronize()
+    log(f"{a.n} rows resident: database {a.n * 128 / 1e9:.1f} GB, index "
+        f"{ix.index_bytes / 1e9:.1f} GB, row store {rs / 1e9:.1f} GB, {time.time() - t0:.1f}s")
+    cq = torch.from_numpy(datagen.make_queries(10_000, seed=datagen.SEED_CALIB)).to(dev)
+    ctruth, _ = brute_force(gdb, cq, 10)
+    t0 = time.time()
+    w, rc = learned.calibrate_fixed_w(ix, cq, ctruth, 10, a.recall + 0.005, hi=1 << 21)
+    del cq, ctruth
+    log(f"fixed w = {w} (calibration recall@10 {rc:.4f}) in {time.time() - t0:.1f}s")
+
+    arrivals = sinusoidal_arrivals(a.duration, a.lo, a.hi, a.period, seed=datagen.SEED_ARRIVALS)
+    R = len(arrivals)
+    queries = datagen.make_queries(R, seed=datagen.SEED_EVAL)
+    ks = np.random.default_rng(datagen.SEED_ARRIVALS).choice(
+        np.array([1, 10, 100], np.uint32), size=R)
+    log(f"{R} requests over {a.duration:.0f}s, rate {a.lo:.0f} .. {a.hi:.0f} per s")
+    srv = Server(ix, w_fixed=w, k_stride=100, max_batch=a.max_batch, slots=a.slots,
+                 route="batch", min_batch=a.min_batch, max_wait_s=a.max_wait)
+    held = torch.cuda.memory_allocated()
+    stats, (ids, d) = srv.run(arrivals, queries, ks, keep_results=True, realtime=True, log=log)
+    log(f"p50 {stats['p50_ms']:.2f} ms, p99 {stats['p99_ms']:.2f} ms, sustained "
+        f"{stats['sustained_qps']:.0f} q/s, mean batch {stats['mean_batch']:.0f}")
+
+    # a sample of the served requests: recall@min(k, 10) against exact kNN, and
+    # each result equal to the request searched alone
+    S = min(a.recall_sample, R)
+    pick = np.linspace(0, R - 1, S).astype(np.int64)
+    hits, same = [], 0
+    for kk in (1, 10, 100):
+        sel = pick[ks[pick] == kk]
+        if not len(sel):
+            continue
+        gsq = torch.from_numpy(queries[sel]).to(dev)
+        kt = min(int(kk), 10)
+        truth, _ = brute_force(gdb, gsq, kt)
+        truth = truth.cpu().numpy().view(np.uint32)
+        hits += [len(set(ids[i, :kt].tolist()) & set(truth[j].tolist())) / kt
+                 for j, i in enumerate(sel)]
+        for j, i in enumerate(sel):
+            ai, ad = ix.search(gsq[j:j + 1], int(kk), w)
+            same += int((ai.cpu().numpy().view(np.uint32)[0] == ids[i, :kk]).all() and
+                        (ad.cpu().numpy().view(np.uint32)[0] == d[i, :kk]).all())
+    out = {"scenario": "serving loop at a recall target", "n": a.n, "requests": R,
+           "duration_s": a.duration, "rate_qps": [a.lo, a.hi], "period_s": a.period,
+           "k_mix": [1, 10, 100], "w_fixed": w, "calib_recall": rc, "route": "batch",
+           "min_batch": a.min_batch, "max_wait_s": a.max_wait,
+           "recall_at_min_k_10": float(np.mean(hits)), "recall_sample": S,
+           "equal_alone": same, "hbm_held_bytes": held, "rowstore_bytes": rs, **stats}
     print(json.dumps(out), flush=True)
 
 

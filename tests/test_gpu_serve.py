@@ -141,3 +141,47 @@ def test_cooperative_scheduler_same_results(env):
     sel = np.arange(0, R, 5)
     ai, ad = alone(env["gix"], env["q"][sel], env["ks"][sel], w[sel])
     assert (ids[sel] == ai).all() and (d[sel] == ad).all()
+
+
+def test_batch_route_banded_equals_alone(oracle):
+    """The batch route at a wide window: one batch of 30,000 requests packed
+    by k, each k class a banded search over the row store (k = 100 in two
+    passes), then smaller batches arriving over time (gathered); every row
+    equals the uneven route's (the gather kernel), the sample the oracle's."""
+    import torch
+    from paper_1209_0410_amd import datagen
+    from paper_1209_0410_amd.index import Index
+    from paper_1209_0410_amd.serve import Server, sinusoidal_arrivals
+    n, R, w = 200_000, 30_000, 3_000
+    db = datagen.make_db(n)
+    gix = Index(torch.from_numpy(db).cuda())
+    gix.attach_rowstore()
+    q = datagen.make_queries(R, seed=25)
+    ks = np.random.default_rng(26).choice([1, 10, 100], size=R).astype(np.uint32)
+    # each k class of the whole batch is large enough to band
+    for kk in (1, 10, 100):
+        m = int((ks == kk).sum())
+        sc = gix.new_scratch(m, 100)
+        assert gix.path(m, int(kk), w, sc.numel()) == 2
+        del sc
+    srv = Server(gix, w_fixed=w, k_stride=100, max_batch=R, slots=1, route="batch")
+    stats, (ids, d) = srv.run(np.zeros(R), q, ks, realtime=False)
+    assert stats["batches"] == 1
+    ref = Server(gix, w_fixed=w, k_stride=100, max_batch=4096, slots=2)
+    _, (rids, rd) = ref.run(np.zeros(R), q, ks, realtime=False)
+    assert (ids == rids).all() and (d == rd).all()
+    sel = np.arange(0, R, 211)
+    oix = oracle.Index(db)
+    for kk in (1, 10, 100):
+        m = sel[ks[sel] == kk]
+        oi, od = oix.search(q[m], int(kk), w)
+        assert (ids[m, :kk] == oi).all() and (d[m, :kk] == od).all()
+    # arrivals over time with a minimum batch: several batches, same rows
+    arr = sinusoidal_arrivals(0.5, 20_000, 80_000, 0.5, seed=27)
+    Rt = min(len(arr), 12_000)
+    srv2 = Server(gix, w_fixed=w, k_stride=100, max_batch=8192, slots=2, route="batch",
+                  min_batch=2048, max_wait_s=0.02)
+    st2, (ids2, d2) = srv2.run(arr[:Rt], q[:Rt], ks[:Rt])
+    assert st2["batches"] > 1
+    assert (ids2 == rids[:Rt]).all() and (d2 == rd[:Rt]).all()
+    assert np.isfinite(st2["p99_ms"])
