@@ -133,7 +133,7 @@ class Server:
 
     def __init__(self, ix, model=None, w_fixed=64, k_stride=100, max_batch=4096, slots=3,
                  budget=None, cfg=None, w_fallback=None, host=None, cpu_workers=0,
-                 k_feature=10, route="uneven", min_batch=1, max_wait_s=0.0):
+                 k_feature=10, route="uneven", min_batch=1, max_wait_s=0.0, band_min=0):
         if route not in ("uneven", "batch"):
             raise ValueError(f"unknown route {route!r}")
         if route == "batch" and host is not None:
@@ -152,6 +152,10 @@ class Server:
         self.cfg = cfg
         self.route = route
         self.min_batch = max(1, int(min_batch))
+        # batch route: a k class of at least band_min requests takes the banded
+        # path whenever each list entry lies in several of its windows, even
+        # below the block count the automatic choice wants (0: automatic)
+        self.band_min = int(band_min)
         self.max_wait_s = float(max_wait_s)
         dev = ix.db.device
         self.slots = [_Slot(ix, self.max_batch, self.k_stride, dev, cfg, route)
@@ -238,8 +242,15 @@ class Server:
                 # with a w per request, w_fixed is the typical w (sizes the work)
                 wp = ctp(slot.w[first:first + m]) if self.model is not None else None
                 wf = self.model.w_hint if self.model is not None else self.w_fixed
-                capi.call("hc_search_batch", self.ix.handle, ctp(qc), m, kv, int(wf), wp,
-                          ctp(ids), ctp(dists), ctp(slot.scratch), slot.scratch.numel(), st)
+                path = capi.HC_PATH_AUTO
+                if (self.band_min and m >= self.band_min and kv <= capi.HC_BAND_K_MAX
+                        and 2.0 * wf * m >= 3.5 * self.ix.n):
+                    path = capi.HC_PATH_BAND
+                capi.call("hc_encode_queries", self.ix.handle, ctp(qc), m, ctp(slot.scratch),
+                          slot.scratch.numel(), st)
+                capi.call("hc_search_encoded_ex", self.ix.handle, ctp(qc), m, kv, int(wf), wp,
+                          ctp(ids), ctp(dists), ctp(slot.scratch), slot.scratch.numel(),
+                          path, st)
                 off += m * kv
             slot.h_out[:2 * tot].copy_(slot.d_out[:2 * tot], non_blocking=True)
             slot.done.record(slot.stream)
@@ -424,6 +435,10 @@ def main(argv=None):
                          "equal-cost comparison of learned and fixed w)")
     ap.add_argument("--min-batch", type=int, default=1)
     ap.add_argument("--max-wait", type=float, default=0.0, help="seconds")
+    ap.add_argument("--alone-sample", type=int, default=200,
+                    help="served requests searched again alone (recall-target scenario)")
+    ap.add_argument("--band-min", type=int, default=0,
+                    help="batch route: band a k class of at least this many requests")
     a = ap.parse_args(argv)
     if a.recall > 0:
         return recall_main(a)
@@ -545,37 +560,47 @@ def recall_main(a):
         np.array([1, 10, 100], np.uint32), size=R)
     log(f"{R} requests over {a.duration:.0f}s, rate {a.lo:.0f} .. {a.hi:.0f} per s")
     srv = Server(ix, w_fixed=w, k_stride=100, max_batch=a.max_batch, slots=a.slots,
-                 route="batch", min_batch=a.min_batch, max_wait_s=a.max_wait)
+                 route="batch", min_batch=a.min_batch, max_wait_s=a.max_wait,
+                 band_min=a.band_min)
     held = torch.cuda.memory_allocated()
     stats, (ids, d) = srv.run(arrivals, queries, ks, keep_results=True, realtime=True, log=log)
     log(f"p50 {stats['p50_ms']:.2f} ms, p99 {stats['p99_ms']:.2f} ms, sustained "
         f"{stats['sustained_qps']:.0f} q/s, mean batch {stats['mean_batch']:.0f}")
+    log("stats " + json.dumps(stats))
 
-    # a sample of the served requests: recall@min(k, 10) against exact kNN, and
-    # each result equal to the request searched alone
+    # a sample of the served requests: recall@min(k, 10) against exact kNN; and
+    # a smaller sample searched again alone (one request per search, on the
+    # uneven path, which splits a wide window over many wavefronts), whose
+    # rows must equal the served ones
     S = min(a.recall_sample, R)
     pick = np.linspace(0, R - 1, S).astype(np.int64)
-    hits, same = [], 0
+    hits = []
     for kk in (1, 10, 100):
         sel = pick[ks[pick] == kk]
         if not len(sel):
             continue
-        gsq = torch.from_numpy(queries[sel]).to(dev)
         kt = min(int(kk), 10)
-        truth, _ = brute_force(gdb, gsq, kt)
+        truth, _ = brute_force(gdb, torch.from_numpy(queries[sel]).to(dev), kt)
         truth = truth.cpu().numpy().view(np.uint32)
         hits += [len(set(ids[i, :kt].tolist()) & set(truth[j].tolist())) / kt
                  for j, i in enumerate(sel)]
-        for j, i in enumerate(sel):
-            ai, ad = ix.search(gsq[j:j + 1], int(kk), w)
-            same += int((ai.cpu().numpy().view(np.uint32)[0] == ids[i, :kk]).all() and
-                        (ad.cpu().numpy().view(np.uint32)[0] == d[i, :kk]).all())
+    log(f"recall@min(k, 10) {np.mean(hits):.4f} on {S} served requests")
+    alone = pick[::max(1, S // a.alone_sample)]
+    same = 0
+    for n_done, i in enumerate(alone):
+        ai, ad = ix.search_uneven(torch.from_numpy(queries[i:i + 1]).to(dev), w=w,
+                                  k=int(ks[i]), k_stride=100)
+        same += int((ai.cpu().numpy().view(np.uint32)[0] == ids[i]).all() and
+                    (ad.cpu().numpy().view(np.uint32)[0] == d[i]).all())
+        if n_done % 50 == 49:
+            log(f"searched alone: {n_done + 1} of {len(alone)}, {same} equal")
     out = {"scenario": "serving loop at a recall target", "n": a.n, "requests": R,
            "duration_s": a.duration, "rate_qps": [a.lo, a.hi], "period_s": a.period,
            "k_mix": [1, 10, 100], "w_fixed": w, "calib_recall": rc, "route": "batch",
-           "min_batch": a.min_batch, "max_wait_s": a.max_wait,
+           "min_batch": a.min_batch, "max_wait_s": a.max_wait, "band_min": a.band_min,
            "recall_at_min_k_10": float(np.mean(hits)), "recall_sample": S,
-           "equal_alone": same, "hbm_held_bytes": held, "rowstore_bytes": rs, **stats}
+           "alone_sample": int(len(alone)), "equal_alone": same, "hbm_held_bytes": held,
+           "rowstore_bytes": rs, **stats}
     print(json.dumps(out), flush=True)
 
 

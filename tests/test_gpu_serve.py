@@ -146,8 +146,9 @@ def test_cooperative_scheduler_same_results(env):
 def test_batch_route_banded_equals_alone(oracle):
     """The batch route at a wide window: one batch of 30,000 requests packed
     by k, each k class a banded search over the row store (k = 100 in two
-    passes), then smaller batches arriving over time (gathered); every row
-    equals the uneven route's (the gather kernel), the sample the oracle's."""
+    passes), then smaller batches arriving over time (classes of at least 512
+    banded, smaller ones gathered); every row equals the uneven route's (the
+    gather kernel), the sample the oracle's."""
     import torch
     from paper_1209_0410_amd import datagen
     from paper_1209_0410_amd.index import Index
@@ -180,7 +181,7 @@ def test_batch_route_banded_equals_alone(oracle):
     arr = sinusoidal_arrivals(0.5, 20_000, 80_000, 0.5, seed=27)
     Rt = min(len(arr), 12_000)
     srv2 = Server(gix, w_fixed=w, k_stride=100, max_batch=8192, slots=2, route="batch",
-                  min_batch=2048, max_wait_s=0.02)
+                  min_batch=2048, max_wait_s=0.02, band_min=512)
     st2, (ids2, d2) = srv2.run(arr[:Rt], q[:Rt], ks[:Rt])
     assert st2["batches"] > 1
     assert (ids2 == rids[:Rt]).all() and (d2 == rd[:Rt]).all()
