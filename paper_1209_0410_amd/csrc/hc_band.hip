@@ -54,9 +54,11 @@ struct BandArgs {
     uint64_t *buf;
     uint32_t cap;
     uint32_t *redo;
+    uint32_t tight;       // first pass: a half also drops pairs above the other half's 16th
 };
 
 constexpr uint32_t kBandCap = 1024;   // k > 16: pairs collected per query (buffer entries)
+constexpr uint32_t kBandTightK = 32;  // k > 16 up to this: the first pass's halves share a bound
 
 struct BandLayout {
     size_t qkeys, pos, counts, order, partial, bound, theta, cnt, redo, buf, total;
@@ -718,7 +720,15 @@ void k_band_dma(BandArgs a)
                 th = own < th ? own : th;
                 th = other < th ? other : th;
             } else if (MODE == kBandHalves) {
-                th = list_bound(L, cq);
+                // the two halves' lists then hold about the curve's 16 nearest:
+                // 16 distinct per curve, enough for a threshold when k is
+                // small (a.tight), and fewer insertions
+                const int own = list_bound(L, cq);
+                th = own;
+                if (a.tight) {
+                    const int other = __shfl_xor(own, 32, 64);
+                    th = other < th ? other : th;
+                }
             }
             const uint32_t rlo = lo > t0 ? std::min<uint32_t>(lo - t0, R) : 0u;
             const uint32_t rhi = hi > t0 ? std::min<uint32_t>(hi - t0, R) : 0u;
@@ -1119,6 +1129,7 @@ hc_status band_search(const IndexView &v, const uint8_t *d_queries, uint32_t nq,
         a.redo = (uint32_t *)(s + L.redo);
         a.buf = (uint64_t *)(s + L.buf);
         a.cap = kBandCap;
+        a.tight = k <= kBandTightK;
     }
     const uint64_t nc = (uint64_t)v.curves * L.nbuckets;
     hipLaunchKernelGGL(k_band_fill, dim3((uint32_t)std::min<uint64_t>(4096, (nc + 255) / 256)),
