@@ -32,6 +32,9 @@ namespace hc {
 
 constexpr int kBucketShift = 8;   // place buckets of 256 list entries
 constexpr int kBandK = 16;        // longest list kept per query and curve
+constexpr uint32_t kMaxSplit = 4; // blocks a group's union may be split over
+constexpr uint64_t kBandFillBlocks = 512;   // blocks that fill MI355X (2 per CU)
+constexpr uint32_t kMQ = 32;             // queries per wavefront
 
 struct BandArgs {
     IndexView v;
@@ -55,10 +58,22 @@ struct BandArgs {
     uint32_t cap;
     uint32_t *redo;
     uint32_t tight;       // first pass: a half also drops pairs above the other half's 16th
+    uint32_t split;       // row-store kernel: blocks per group (the union's tiles dealt out)
 };
 
 constexpr uint32_t kBandCap = 1024;   // k > 16: pairs collected per query (buffer entries)
 constexpr uint32_t kBandTightK = 32;  // k > 16 up to this: the first pass's halves share a bound
+
+// Blocks a group's union is dealt out over: the least number that gives the
+// grid kBandFillBlocks blocks, at most kMaxSplit.  Larger groups give fewer
+// blocks, so the 256-query groups bound it for any window.
+inline uint32_t band_split(uint32_t curves, uint32_t nq, uint32_t block_q)
+{
+    const uint64_t blocks = ((uint64_t)nq + block_q - 1) / block_q * curves;
+    uint32_t sp = 1;
+    while (sp < kMaxSplit && blocks * sp < kBandFillBlocks) sp++;
+    return sp;
+}
 
 struct BandLayout {
     size_t qkeys, pos, counts, order, partial, bound, theta, cnt, redo, buf, total;
@@ -83,7 +98,8 @@ inline BandLayout band_layout(uint32_t curves, uint64_t n, uint32_t nq, uint32_t
     L.order = off;
     off = align256(off + sizeof(uint32_t) * (size_t)curves * nq);
     L.partial = off;
-    off = align256(off + sizeof(uint64_t) * (size_t)nq * curves * (two ? 2 * kBandK : kBandK));
+    off = align256(off + sizeof(uint64_t) * (size_t)nq * curves * band_split(curves, nq, 256) *
+                         (two ? 2 * kBandK : kBandK));
     L.bound = off;
     off = align256(off + sizeof(uint32_t) * (size_t)nq);
     L.theta = L.cnt = L.redo = L.buf = 0;
@@ -162,11 +178,17 @@ __global__ __launch_bounds__(256) void k_band_scatter(BandArgs a)
 // Only a pair that passes pays for the exact distance, the window test, the id
 // and the insertion (ties are settled by the id there).
 // ---------------------------------------------------------------------------
-constexpr int kMQ = 32;             // queries per wavefront
+
 // Wavefronts per block: 8 shares each streamed row among 256 queries (large
 // windows, where the rows dominate); 4 keeps blocks small and many (windows
 // below kBandWideW, where a block's union is mostly the span of its places).
 constexpr uint32_t kBandWideW = 8192;
+
+// queries per block of the banded kernels for a window w
+__host__ __device__ constexpr uint32_t band_block_q(uint32_t w)
+{
+    return w < kBandWideW ? 4 * kMQ : 8 * kMQ;
+}
 constexpr uint32_t kNoRow = 0xFFFFFFFFu;
 
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -562,7 +584,9 @@ __device__ inline void unroll_blocks(F &f)
 //               key is appended to the query's buffer (second pass for k > 16).
 constexpr int kBandLists = 0, kBandHalves = 1, kBandThresh = 2;
 
-template <int KR, int NW, int MODE>
+// SPLIT: each group's union is dealt out over a.split blocks (small batches);
+// without it the block decomposition folds to one block per group.
+template <int KR, int NW, int MODE, bool SPLIT>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(KR > 10 ? 3 : 4)))
 void k_band_dma(BandArgs a)
 {
@@ -579,7 +603,12 @@ void k_band_dma(BandArgs a)
     const uint32_t C = a.v.curves;
     const uint64_t n = a.v.n;
     const uint32_t groups = (a.nq + kBlockQ - 1) / kBlockQ;
-    const uint32_t grp = blockIdx.x % groups, c = blockIdx.x / groups;
+    // curve-major; the split blocks of a group are neighbours and take the
+    // tiles of its union in turn (tile i of the middle-out order to block
+    // i mod split), so each sees every wavefront busy about as often
+    const uint32_t nsplit = SPLIT ? a.split : 1u, per_c = groups * nsplit;
+    const uint32_t c = blockIdx.x / per_c, grp = (blockIdx.x % per_c) / nsplit,
+                   sub = SPLIT ? blockIdx.x % nsplit : 0u;
 
     const uint64_t slot = (uint64_t)grp * kBlockQ + (uint64_t)wv * kMQ + qn;
     const bool live = slot < a.nq;
@@ -643,7 +672,11 @@ void k_band_dma(BandArgs a)
     // DMA into bslot every 8 tiles
     int ext = INT32_MAX;
     uint64_t theta = kNone;     // kBandThresh: the query's threshold key
-    if (MODE == kBandLists) {
+    // the bound is shared between curves in the one-pass search, and in the
+    // first pass of k <= 32 (a.tight), where it is the k-th of a curve's 32
+    // candidates
+    const bool shared = MODE == kBandLists || (MODE == kBandHalves && a.tight);
+    if (shared) {
         const uint32_t b = live ? __hip_atomic_load(a.bound + q, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT)
                                 : kEmpty;
@@ -680,7 +713,7 @@ void k_band_dma(BandArgs a)
     // wavefronts 0, 1, 2 the crow2, id and parity parts
     auto issue = [&](uint32_t j, uint32_t sj) {
         BandStage<NW> &S = st[sj];
-        const uint64_t e0 = tile_start(j);
+        const uint64_t e0 = tile_start(j * nsplit + sub);
 #pragma unroll
         for (int k = 0; k < 2; k++) {
             const uint32_t m = 2 * wv + k;
@@ -705,7 +738,7 @@ void k_band_dma(BandArgs a)
 
     // tile i of the union, from stage si
     auto do_tile = [&](uint32_t i, uint32_t si) {
-        const uint32_t t0 = tile_start(i);
+        const uint32_t t0 = tile_start(i * nsplit + sub);
         if (!(t0 < u1 && (uint64_t)t0 + R > u0)) return;       // wavefront-uniform
         {
             BandStage<NW> &S = st[si];
@@ -724,7 +757,7 @@ void k_band_dma(BandArgs a)
                 // 16 distinct per curve, enough for a threshold when k is
                 // small (a.tight), and fewer insertions
                 const int own = list_bound(L, cq);
-                th = own;
+                th = own < th ? own : th;
                 if (a.tight) {
                     const int other = __shfl_xor(own, 32, 64);
                     th = other < th ? other : th;
@@ -816,19 +849,20 @@ void k_band_dma(BandArgs a)
     // barrier, into the stages group g - 1 used, so one wait (everything
     // issued so far) and one barrier serve kTPB tiles.  The bound copied
     // with group g + 1 (every 4 groups) is read with it.
-    const uint32_t NG = (T + kTPB - 1) / kTPB;
+    const uint32_t TS = T > sub ? (T - 1 - sub) / nsplit + 1 : 0u;   // this block's tiles
+    const uint32_t NG = (TS + kTPB - 1) / kTPB;
     auto issue_group = [&](uint32_t g) {
 #pragma unroll
         for (int j = 0; j < kTPB; j++) {
             const uint32_t t = g * kTPB + j;
-            if (t < T) issue(t, (g & 1) * kTPB + j);
+            if (t < TS) issue(t, (g & 1) * kTPB + j);
         }
     };
     if (NG > 0) issue_group(0);
     for (uint32_t g = 0; g < NG; g++) {
         __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0)
         __builtin_amdgcn_s_barrier();
-        if (MODE == kBandLists && g >= 1 && ((g - 1) & 3) == 3) {
+        if (shared && g >= 1 && ((g - 1) & 3) == 3) {
             uint32_t b = lds_b32(lds_addr(&bslot[wv][qn]));
             asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(b));
             if (live && b != kEmpty) {
@@ -837,7 +871,7 @@ void k_band_dma(BandArgs a)
             }
         }
         if (g + 1 < NG) {
-            if (MODE == kBandLists && (g & 3) == 3 && lane < kMQ)
+            if (shared && (g & 3) == 3 && lane < kMQ)
                 dma4(a.bound + q, &bslot[wv][0]);
             asm volatile("" ::: "memory");
             issue_group(g + 1);
@@ -845,7 +879,7 @@ void k_band_dma(BandArgs a)
 #pragma unroll
         for (int j = 0; j < kTPB; j++) {
             const uint32_t t = g * kTPB + j;
-            if (t < T) do_tile(t, (g & 1) * kTPB + j);
+            if (t < TS) do_tile(t, (g & 1) * kTPB + j);
         }
     }
 
@@ -853,9 +887,33 @@ void k_band_dma(BandArgs a)
     if (MODE == kBandHalves) {
         // both halves' lists: entries [16 h, 16 h + 16) of the query's 32 for curve c
         if (live) {
-            uint64_t *out = a.partial + ((uint64_t)q * C + c) * (2 * kBandK) + kBandK * h;
+            uint64_t *out = a.partial + (((uint64_t)q * C + c) * nsplit + sub) * (2 * kBandK) +
+                            kBandK * h;
 #pragma unroll
             for (int i = 0; i < KR; i++) out[i] = L[i];
+        }
+        if (a.tight) {
+            // the k-th of the two halves' lists (32 distinct ids of the
+            // union, in this block's rows of the curve): a key's rank is its
+            // index plus the other list's keys below it.  These 32 stay among
+            // the threshold's candidates, so the threshold exists and is at
+            // or below this bound; and the union's k nearest are at or below it
+            uint64_t M[KR];
+#pragma unroll
+            for (int i = 0; i < KR; i++) M[i] = shfl_xor_u64(L[i], 32);
+            uint64_t kth = kNone;
+#pragma unroll
+            for (int i = 0; i < KR; i++) {
+                uint32_t below_l = 0, below_m = 0;
+#pragma unroll
+                for (int j = 0; j < KR; j++) {
+                    below_l += M[j] < L[i] ? 1u : 0u;
+                    below_m += L[j] < M[i] ? 1u : 0u;
+                }
+                if (i + below_l == a.k - 1 && L[i] != kNone) kth = L[i];
+                if (i + below_m == a.k - 1 && M[i] != kNone) kth = M[i];
+            }
+            if (live && h == 0 && kth != kNone) atomicMin(a.bound + q, (uint32_t)(kth >> 32));
         }
         return;
     }
@@ -870,7 +928,7 @@ void k_band_dma(BandArgs a)
         }
     }
     if (live && h == 0) {
-        uint64_t *out = a.partial + ((uint64_t)q * C + c) * a.k;
+        uint64_t *out = a.partial + (((uint64_t)q * C + c) * nsplit + sub) * a.k;
         uint64_t kth = kNone;
 #pragma unroll
         for (int i = 0; i < KR; i++) {
@@ -890,11 +948,11 @@ void k_band_dma(BandArgs a)
 constexpr int kMergeWaves = 4;
 __global__ __launch_bounds__(64 * kMergeWaves) void k_band_merge(BandArgs a)
 {
-    __shared__ uint64_t lists[kMergeWaves][kMaxCurves * kBandK];
+    __shared__ uint64_t lists[kMergeWaves][kMaxCurves * kMaxSplit * kBandK];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint32_t q = blockIdx.x * kMergeWaves + wv;
     if (q >= a.nq) return;                 // the whole wavefront; no barrier follows
-    const uint32_t C = a.v.curves, k = a.k;
+    const uint32_t C = a.v.curves * a.split, k = a.k;     // lists: per curve and split block
     const uint32_t nkeys = C * k;
     const uint64_t *src = a.partial + (uint64_t)q * nkeys;
     uint64_t *ls = lists[wv];
@@ -907,9 +965,9 @@ __global__ __launch_bounds__(64 * kMergeWaves) void k_band_merge(BandArgs a)
     uint64_t head = mine ? ls[lane * k] : kNone;
     const uint64_t o = (uint64_t)q * k;
     for (uint32_t j = 0; j < k; j++) {
-        uint64_t m = head;                 // minimum over lanes 0..7 (C <= 8)
+        uint64_t m = head;                 // minimum over lanes 0..15 (C <= 16)
 #pragma unroll
-        for (int x = 1; x < kMaxCurves; x <<= 1) {
+        for (int x = 1; x < kMaxCurves * (int)kMaxSplit; x <<= 1) {
             const uint64_t y = shfl_xor_u64(m, x);
             m = y < m ? y : m;
         }
@@ -934,7 +992,7 @@ __global__ __launch_bounds__(64) void k_band_theta(BandArgs a)
     __shared__ TopKShared sh;
     const int lane = threadIdx.x;
     const uint32_t q = blockIdx.x;
-    const uint32_t m = a.v.curves * 2 * kBandK;
+    const uint32_t m = a.v.curves * a.split * 2 * kBandK;
     const uint64_t *src = a.partial + (uint64_t)q * m;
     WaveTopK<0> tk;
     tk.init(a.k, &sh, lane);
@@ -1051,20 +1109,29 @@ size_t band_scratch_bytes(uint32_t curves, uint64_t n, uint32_t nq, uint32_t k_m
     return band_layout(curves, n, nq, k_max).total;
 }
 
+template <int NW, bool SPLIT>
+static void launch_dma_lists(uint32_t k, dim3 grid, dim3 block, const BandArgs &a, hipStream_t st)
+{
+    if (k == 1) hipLaunchKernelGGL((k_band_dma<1, NW, kBandLists, SPLIT>), grid, block, 0, st, a);
+    else if (k <= 4)
+        hipLaunchKernelGGL((k_band_dma<4, NW, kBandLists, SPLIT>), grid, block, 0, st, a);
+    else if (k <= 10)
+        hipLaunchKernelGGL((k_band_dma<10, NW, kBandLists, SPLIT>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_band_dma<kBandK, NW, kBandLists, SPLIT>), grid, block, 0, st, a);
+}
+
 template <int NW>
 static void launch_band(const IndexView &v, uint32_t k, uint32_t nq, const BandArgs &a,
                         hipStream_t st)
 {
     const uint32_t blocks = (uint32_t)(((uint64_t)nq + NW * kMQ - 1) / (NW * kMQ)) * v.curves;
-    const dim3 grid(blocks), block(64 * NW);
+    const dim3 block(64 * NW);
     if (v.rows[0]) {
-        if (k == 1) hipLaunchKernelGGL((k_band_dma<1, NW, kBandLists>), grid, block, 0, st, a);
-        else if (k <= 4)
-            hipLaunchKernelGGL((k_band_dma<4, NW, kBandLists>), grid, block, 0, st, a);
-        else if (k <= 10)
-            hipLaunchKernelGGL((k_band_dma<10, NW, kBandLists>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_band_dma<kBandK, NW, kBandLists>), grid, block, 0, st, a);
+        const dim3 grid(blocks * a.split);
+        if (a.split > 1) launch_dma_lists<NW, true>(k, grid, block, a, st);
+        else launch_dma_lists<NW, false>(k, grid, block, a, st);
     } else {
+        const dim3 grid(blocks);
         if (k == 1) hipLaunchKernelGGL((k_band<1, NW>), grid, block, 0, st, a);
         else if (k <= 4) hipLaunchKernelGGL((k_band<4, NW>), grid, block, 0, st, a);
         else if (k <= 10) hipLaunchKernelGGL((k_band<10, NW>), grid, block, 0, st, a);
@@ -1079,11 +1146,16 @@ static void launch_band_two(const IndexView &v, uint32_t nq, const BandArgs &a, 
                             hipStream_t st)
 {
     const uint32_t blocks = (uint32_t)(((uint64_t)nq + NW * kMQ - 1) / (NW * kMQ)) * v.curves;
-    const dim3 grid(blocks), block(64 * NW);
-    if (mode == kBandHalves)
-        hipLaunchKernelGGL((k_band_dma<kBandK, NW, kBandHalves>), grid, block, 0, st, a);
+    const dim3 grid(blocks * a.split), block(64 * NW);
+    const bool sp = a.split > 1;
+    if (mode == kBandHalves && sp)
+        hipLaunchKernelGGL((k_band_dma<kBandK, NW, kBandHalves, true>), grid, block, 0, st, a);
+    else if (mode == kBandHalves)
+        hipLaunchKernelGGL((k_band_dma<kBandK, NW, kBandHalves, false>), grid, block, 0, st, a);
+    else if (sp)
+        hipLaunchKernelGGL((k_band_dma<1, NW, kBandThresh, true>), grid, block, 0, st, a);
     else
-        hipLaunchKernelGGL((k_band_dma<1, NW, kBandThresh>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((k_band_dma<1, NW, kBandThresh, false>), grid, block, 0, st, a);
 }
 
 uint64_t band_blocks(uint32_t curves, uint32_t nq, uint32_t w)
@@ -1131,6 +1203,13 @@ hc_status band_search(const IndexView &v, const uint8_t *d_queries, uint32_t nq,
         a.cap = kBandCap;
         a.tight = k <= kBandTightK;
     }
+    // a small batch makes few groups; over the row store each group's union
+    // is then dealt out over up to kMaxSplit blocks, so that the grid has
+    // at least kBandFillBlocks blocks (two per CU)
+    // (one-pass searches only: in the first pass of k > 16 every block
+    // builds its lists from nothing, so more blocks per group mean more
+    // insertions)
+    a.split = (v.rows[0] && !two) ? band_split(v.curves, nq, band_block_q(w_fixed)) : 1u;
     const uint64_t nc = (uint64_t)v.curves * L.nbuckets;
     hipLaunchKernelGGL(k_band_fill, dim3((uint32_t)std::min<uint64_t>(4096, (nc + 255) / 256)),
                        dim3(256), 0, st, a.counts, nc, 0u);
