@@ -278,6 +278,9 @@ static hc_status sample_levels(const IndexView &v, uint32_t c, hipStream_t st)
         hipLaunchKernelGGL(k_sample_keys, dim3(blocks_for(v.len[l], 256)), dim3(256), 0, st,
                            v.lvl[c][0], stride, (Key *)v.lvl[c][l], v.len[l]);
     }
+    if (v.len_sub)
+        hipLaunchKernelGGL(k_sample_keys, dim3(blocks_for(v.len_sub, 256)), dim3(256), 0, st,
+                           v.lvl[c][0], (uint64_t)kSub, (Key *)v.sub[c], v.len_sub);
     return last_hip();
 }
 

@@ -18,6 +18,13 @@ __device__ inline uint64_t shfl_xor_u64(uint64_t v, int m)
     return ((uint64_t)hi << 32) | lo;
 }
 
+__device__ inline uint64_t readlane_u64(uint64_t v, int l)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ inline uint64_t wave_min_u64(uint64_t v)
 {
 #pragma unroll
@@ -31,6 +38,11 @@ __device__ inline uint64_t wave_min_u64(uint64_t v)
 // Number of keys below the query key in each curve c < C, for the curves
 // c = first + j * step (j < CPW) handled by the calling wave.  Wave-uniform
 // control flow; cnt[j] is the position of curve first + j * step.
+// The table's upper levels are read 64 keys wide (1 KiB per curve, mostly
+// cache hits); the last two steps, from level 1 (every 64th key) through the
+// every-8th-key level to the keys, read 8 keys (128 B) per curve, lane
+// 8j + r holding key r of curve j's block: one load serves every curve and
+// the HBM bytes of a location drop from 1 KiB to 256 B per curve.
 // Every load is issued unconditionally from an address inside the table
 // (entry 0 of curve 0 standing in for slots that do not exist) and masked
 // afterwards, so that the loads of all curves at one level are in flight
@@ -85,7 +97,7 @@ __device__ inline void locate(const IndexView &v, const Key *qk_row, uint32_t fi
             cnt[j] = (uint64_t)__popcll(__ballot(less));
         }
     }
-    for (int L = (int)D; L >= 1; L--) {
+    for (int L = (int)D; L >= 2; L--) {
         // cnt = entries of level L below qkey, so the answer at level L-1 lies in
         // the 64 entries from 64*(cnt-1) (entry 64*cnt is >= qkey); cnt = 0
         // means every key is >= qkey.
@@ -108,6 +120,37 @@ __device__ inline void locate(const IndexView &v, const Key *qk_row, uint32_t fi
             cnt[j] = cnt[j] ? base[j] + (uint64_t)__popcll(m) : 0;
         }
     }
+    if (D == 0) return;   // the top table was the list itself
+    // the same rule 8 keys wide: cnt entries of the coarser level below the key
+    // put the answer in the 8 entries from 8 (cnt - 1) of the finer one
+    const int jl = lane >> 3, r = lane & 7;
+    uint64_t c1 = 0;
+    Key mq = qk[0];
+    const Key *sb = v.sub[cc[0]];
+    const Key *kb = v.lvl[cc[0]][0];
+    bool lon = false;
+#pragma unroll
+    for (int j = 0; j < CPW; j++) {
+        if (jl == j) {
+            c1 = cnt[j];
+            mq = qk[j];
+            sb = v.sub[cc[j]];
+            kb = v.lvl[cc[j]][0];
+            lon = on[j];
+        }
+    }
+    const uint64_t sbase = c1 ? (c1 - 1) * kSub : 0;
+    const bool sok = lon & (c1 != 0) & (sbase + r < v.len_sub);
+    const Key sk = sb[sok ? sbase + r : 0];
+    const uint64_t sm = __ballot(sok & key_less_nb(sk, mq));
+    const uint64_t cs = c1 ? sbase + (uint64_t)__popcll((sm >> (8 * jl)) & 0xFFull) : 0;
+    const uint64_t kbase = cs ? (cs - 1) * kSub : 0;
+    const bool kok = lon & (cs != 0) & (kbase + r < v.n);
+    const Key kk = kb[kok ? kbase + r : 0];
+    const uint64_t km = __ballot(kok & key_less_nb(kk, mq));
+    const uint64_t p = cs ? kbase + (uint64_t)__popcll((km >> (8 * jl)) & 0xFFull) : 0;
+#pragma unroll
+    for (int j = 0; j < CPW; j++) cnt[j] = readlane_u64(p, 8 * j);
 }
 
 // Sum over 16 bytes of (q - x)^2 = q.q + x.x - 2 q.x with 4-byte dot products

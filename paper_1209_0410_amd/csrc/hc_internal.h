@@ -12,6 +12,7 @@ constexpr int kDim = 128;          // bytes per vector
 constexpr int kDpc = 16;           // dims per curve
 constexpr int kMaxCurves = 8;
 constexpr int kFan = 64;           // fan-out of the sampled-key table = wave size
+constexpr int kSub = 8;            // fan-out of the last two steps (8 keys = 128 B)
 constexpr int kMaxLevels = 6;      // 64^6 > 2^32 rows
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint64_t kNone = ~0ull;  // packed (dist << 32 | id) of an empty slot
@@ -28,6 +29,8 @@ struct IndexView {
     uint32_t levels;                          // D: top table is level D
     uint64_t len[kMaxLevels + 1];             // entries of level L (len[0] = n)
     const Key *lvl[kMaxCurves][kMaxLevels + 1];   // lvl[c][0] = sorted keys
+    uint64_t len_sub;                         // entries of sub (0 when levels == 0)
+    const Key *sub[kMaxCurves];               // every kSub-th key of curve c
     const uint32_t *ids[kMaxCurves];
     uint16_t perm[kMaxCurves * kDpc];
     uint32_t identity;                        // perm is 16c + j
@@ -53,13 +56,16 @@ struct hc_index {
 
 namespace hc {
 
-// Layout of the index buffer: per curve, keys[n], ids[n], then levels 1..D;
-// every array starts on a 256-byte boundary.
+// Layout of the index buffer: per curve, keys[n], ids[n], levels 1..D (level
+// L holds every 64^L-th key), then, when D >= 1, sub[ceil(n / 8)] (every 8th
+// key); every array starts on a 256-byte boundary.
 struct Layout {
     uint32_t levels;
     uint64_t len[kMaxLevels + 1];
+    uint64_t len_sub;
     size_t keys_off[kMaxCurves], ids_off[kMaxCurves];
     size_t lvl_off[kMaxCurves][kMaxLevels + 1];
+    size_t sub_off[kMaxCurves];
     size_t total;
 };
 
@@ -75,6 +81,7 @@ inline Layout make_layout(uint32_t curves, uint64_t n)
         D++;
     }
     L.levels = D;
+    L.len_sub = D ? (n + kSub - 1) / kSub : 0;
     size_t off = 0;
     for (uint32_t c = 0; c < curves; c++) {
         L.keys_off[c] = off;
@@ -86,6 +93,8 @@ inline Layout make_layout(uint32_t curves, uint64_t n)
             L.lvl_off[c][l] = off;
             off = align256(off + sizeof(Key) * L.len[l]);
         }
+        L.sub_off[c] = off;
+        off = align256(off + sizeof(Key) * L.len_sub);
     }
     L.total = off;
     return L;

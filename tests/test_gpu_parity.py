@@ -146,7 +146,7 @@ def test_deterministic_and_batch_independent(c1):
     assert (u32(alone_ids)[0] == u32(a_ids)[17]).all()
 
 
-@pytest.mark.parametrize("n", [1, 7, 64, 65, 1000, 4097, 65537])
+@pytest.mark.parametrize("n", [1, 7, 64, 65, 521, 1000, 4097, 65537])
 def test_small_shapes_bit_exact(oracle, torch_mod, n):
     from paper_1209_0410_amd import datagen
     from paper_1209_0410_amd.index import Index
