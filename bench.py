@@ -76,7 +76,7 @@ def parse():
     ap.add_argument("--secondary-n", type=int, default=10_000_000,
                     help="rows of the secondary legs (a prefix of the database); 0 = skip them")
     ap.add_argument("--sweep", default="16,64,256,1024,4096")
-    ap.add_argument("--sweep-steps", type=int, default=3)
+    ap.add_argument("--sweep-steps", type=int, default=10)
     ap.add_argument("--uneven", type=int, default=200_000,
                     help="queries of the uneven batch (per-query w and k); 0 = skip")
     ap.add_argument("--f4", type=int, default=1,
@@ -98,15 +98,21 @@ def parse():
 # timing helpers
 # ---------------------------------------------------------------------------
 
-def timed(fn, steps, warmup, stream):
-    """Runs fn(ev, stream) `steps` times after `warmup` untimed runs.  fn records
-    ev[0] at the step's start, ev[1] before the search call, ev[2] at the end;
-    a search step also hands ev[3], ev[4] to the library, which records them
-    around the search's main kernel.  Returns per-step lists (ms)."""
+def timed(fn, steps, warmup, stream, warm_s=0.0):
+    """Runs fn(ev, stream) `steps` times after `warmup` untimed runs, and after
+    further untimed runs until warm_s seconds have passed (a short step that
+    follows host-only work would otherwise be timed before the clocks rise).
+    fn records ev[0] at the step's start, ev[1] before the search call, ev[2]
+    at the end; a search step also hands ev[3], ev[4] to the library, which
+    records them around the search's main kernel.  Returns per-step lists (ms)."""
     import torch
+    t0 = time.perf_counter()
     for _ in range(warmup):
         fn(None, stream)
     torch.cuda.synchronize()
+    while time.perf_counter() - t0 < warm_s:
+        fn(None, stream)
+        torch.cuda.synchronize()
     marks = []
     t_wall = time.perf_counter()
     for _ in range(steps):
@@ -800,7 +806,8 @@ def run_secondary(a, gdb_all, db, k, dev, stream):
 
     sweep = []
     for w in sorted({int(x) for x in a.sweep.split(",") if x}):
-        t = summary(timed(fixed_step(ix, gq, k, w, out, sc, forced), a.sweep_steps, 1, stream))
+        t = summary(timed(fixed_step(ix, gq, k, w, out, sc, forced), a.sweep_steps, 1, stream,
+                          warm_s=0.25))
         p = path_name(forced if forced else ix.path(nq, k, w, sc.numel()))
         wk = work.of(w=w)
         roof = roofline_of(p, wk, t["main_kernel_ms"])

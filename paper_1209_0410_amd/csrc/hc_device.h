@@ -401,6 +401,8 @@ __device__ inline uint64_t make_windows(const IndexView &v, const uint64_t (&pos
 // per step, one coalesced load of 64 window ids, then 8 lanes per 128-byte
 // row (16-byte loads), dot4 arithmetic and a 3-step lane-xor reduction; each
 // lane ends up with one slot's packed key, handed to sink.push (kNone past s1).
+// The next step's ids are loaded together with this step's rows, so a step
+// waits for one memory latency, not two.
 template <int G, class Sink>
 __device__ inline void stream_slots(const uint8_t *db, const WindowSet *ws, uint64_t s0,
                                     uint64_t s1, const uint4 &qv, uint32_t qq, int lane,
@@ -410,19 +412,26 @@ __device__ inline void stream_slots(const uint8_t *db, const WindowSet *ws, uint
     uint64_t off[kMaxCurves];   // uniform copies of the prefix sums
 #pragma unroll
     for (int c = 0; c < kMaxCurves; c++) off[c] = ws->off[c];
-    for (uint64_t base = s0; base < s1; base += 64 * G) {
-        uint32_t myid[G];
+    auto load_ids = [&](uint64_t base, uint32_t (&ids)[G]) {
 #pragma unroll
         for (int g = 0; g < G; g++) {
             const uint64_t s = base + 64 * g + lane;
-            myid[g] = 0;
+            ids[g] = 0;
             if (s < s1) {
                 int c = 0;
 #pragma unroll
                 for (int j = 1; j < kMaxCurves; j++) c += s >= off[j] ? 1 : 0;
-                myid[g] = ws->base[c][s - ws->off[c]];
+                ids[g] = ws->base[c][s - ws->off[c]];
             }
         }
+    };
+    uint32_t next[G];
+    load_ids(s0, next);
+    for (uint64_t base = s0; base < s1; base += 64 * G) {
+        uint32_t myid[G];
+#pragma unroll
+        for (int g = 0; g < G; g++) myid[g] = next[g];
+        load_ids(base + 64 * G, next);
         // in step t of group g, lanes 8r..8r+7 read the row of slot 64 g + 8 t + r
         uint4 x[8 * G];
 #pragma unroll
