@@ -97,8 +97,9 @@ const char *hc_status_str(hc_status s);
 
 /* Bytes of the index buffer for n vectors, and of the scratch buffer that
  * hc_build_index needs.  The index holds, per curve, n keys (16 B), n ids
- * (4 B), a 64-ary table of sampled keys (about n/63 keys) and every 8th key
- * (n/8 keys) that the search uses to locate a key in a few coalesced probes. */
+ * (4 B), a 64-ary table of sampled keys (about n/63 keys), every 8th key and
+ * every 512th key (n/8 + n/512 keys) that the search uses to locate a key in
+ * a few coalesced probes. */
 hc_status hc_index_bytes(const hc_params *p, uint64_t n, size_t *index_bytes,
                          size_t *build_scratch_bytes);
 

@@ -281,6 +281,9 @@ static hc_status sample_levels(const IndexView &v, uint32_t c, hipStream_t st)
     if (v.len_sub)
         hipLaunchKernelGGL(k_sample_keys, dim3(blocks_for(v.len_sub, 256)), dim3(256), 0, st,
                            v.lvl[c][0], (uint64_t)kSub, (Key *)v.sub[c], v.len_sub);
+    if (v.len_sub2)
+        hipLaunchKernelGGL(k_sample_keys, dim3(blocks_for(v.len_sub2, 256)), dim3(256), 0, st,
+                           v.lvl[c][0], (uint64_t)(kFan * kSub), (Key *)v.sub2[c], v.len_sub2);
     return last_hip();
 }
 

@@ -38,11 +38,12 @@ __device__ inline uint64_t wave_min_u64(uint64_t v)
 // Number of keys below the query key in each curve c < C, for the curves
 // c = first + j * step (j < CPW) handled by the calling wave.  Wave-uniform
 // control flow; cnt[j] is the position of curve first + j * step.
-// The table's upper levels are read 64 keys wide (1 KiB per curve, mostly
-// cache hits); the last two steps, from level 1 (every 64th key) through the
-// every-8th-key level to the keys, read 8 keys (128 B) per curve, lane
-// 8j + r holding key r of curve j's block: one load serves every curve and
-// the HBM bytes of a location drop from 1 KiB to 256 B per curve.
+// The table's upper levels, down to level 2 (every 4096th key), are read 64
+// keys wide (1 KiB per curve, cache hits); the last four steps, through every
+// 512th key, level 1, every 8th key and the keys, read 8 keys (128 B) per
+// curve, lane 8j + r holding key r of curve j's block: one load serves every
+// curve, and the bytes from beyond the cache drop from 2 KiB to 512 B per
+// curve.
 // Every load is issued unconditionally from an address inside the table
 // (entry 0 of curve 0 standing in for slots that do not exist) and masked
 // afterwards, so that the loads of all curves at one level are in flight
@@ -97,7 +98,8 @@ __device__ inline void locate(const IndexView &v, const Key *qk_row, uint32_t fi
             cnt[j] = (uint64_t)__popcll(__ballot(less));
         }
     }
-    for (int L = (int)D; L >= 2; L--) {
+    // 64 keys wide down to level 2 (its cnt), or to the top table
+    for (int L = (int)D; L >= 3; L--) {
         // cnt = entries of level L below qkey, so the answer at level L-1 lies in
         // the 64 entries from 64*(cnt-1) (entry 64*cnt is >= qkey); cnt = 0
         // means every key is >= qkey.
@@ -121,36 +123,44 @@ __device__ inline void locate(const IndexView &v, const Key *qk_row, uint32_t fi
         }
     }
     if (D == 0) return;   // the top table was the list itself
-    // the same rule 8 keys wide: cnt entries of the coarser level below the key
-    // put the answer in the 8 entries from 8 (cnt - 1) of the finer one
+    // Then 8 keys wide, lane 8j + r on key r of curve j's block: from level 2
+    // through every 512th key, level 1 and every 8th key to the keys (from
+    // level 1 when it is the top table).  The same rule: c entries of the
+    // coarser level below the key put the answer in the 8 entries from
+    // 8 (c - 1) of the finer one.
     const int jl = lane >> 3, r = lane & 7;
-    uint64_t c1 = 0;
+    uint64_t c = 0;
     Key mq = qk[0];
-    const Key *sb = v.sub[cc[0]];
-    const Key *kb = v.lvl[cc[0]][0];
+    const Key *f2 = v.sub2[cc[0]], *f1 = v.lvl[cc[0]][1];
+    const Key *f0 = v.sub[cc[0]], *fk = v.lvl[cc[0]][0];
     bool lon = false;
 #pragma unroll
     for (int j = 0; j < CPW; j++) {
         if (jl == j) {
-            c1 = cnt[j];
+            c = cnt[j];
             mq = qk[j];
-            sb = v.sub[cc[j]];
-            kb = v.lvl[cc[j]][0];
+            f2 = v.sub2[cc[j]];
+            f1 = v.lvl[cc[j]][1];
+            f0 = v.sub[cc[j]];
+            fk = v.lvl[cc[j]][0];
             lon = on[j];
         }
     }
-    const uint64_t sbase = c1 ? (c1 - 1) * kSub : 0;
-    const bool sok = lon & (c1 != 0) & (sbase + r < v.len_sub);
-    const Key sk = sb[sok ? sbase + r : 0];
-    const uint64_t sm = __ballot(sok & key_less_nb(sk, mq));
-    const uint64_t cs = c1 ? sbase + (uint64_t)__popcll((sm >> (8 * jl)) & 0xFFull) : 0;
-    const uint64_t kbase = cs ? (cs - 1) * kSub : 0;
-    const bool kok = lon & (cs != 0) & (kbase + r < v.n);
-    const Key kk = kb[kok ? kbase + r : 0];
-    const uint64_t km = __ballot(kok & key_less_nb(kk, mq));
-    const uint64_t p = cs ? kbase + (uint64_t)__popcll((km >> (8 * jl)) & 0xFFull) : 0;
+    auto step8 = [&](const Key *fine, uint64_t len) {
+        const uint64_t base = c ? (c - 1) * kSub : 0;
+        const bool ok = lon & (c != 0) & (base + r < len);
+        const Key k = fine[ok ? base + r : 0];
+        const uint64_t m = __ballot(ok & key_less_nb(k, mq));
+        c = c ? base + (uint64_t)__popcll((m >> (8 * jl)) & 0xFFull) : 0;
+    };
+    if (D >= 2) {
+        step8(f2, v.len_sub2);
+        step8(f1, v.len[1]);
+    }
+    step8(f0, v.len_sub);
+    step8(fk, v.n);
 #pragma unroll
-    for (int j = 0; j < CPW; j++) cnt[j] = readlane_u64(p, 8 * j);
+    for (int j = 0; j < CPW; j++) cnt[j] = readlane_u64(c, 8 * j);
 }
 
 // Sum over 16 bytes of (q - x)^2 = q.q + x.x - 2 q.x with 4-byte dot products

@@ -44,12 +44,14 @@ hc_status fill_view(const hc_params *p, const uint8_t *d_db, uint64_t n, void *d
     v->levels = L.levels;
     for (uint32_t l = 0; l <= L.levels; l++) v->len[l] = L.len[l];
     v->len_sub = L.len_sub;
+    v->len_sub2 = L.len_sub2;
     uint8_t *base = (uint8_t *)d_index;
     for (uint32_t c = 0; c < p->curves; c++) {
         for (uint32_t l = 0; l <= L.levels; l++)
             v->lvl[c][l] = (const Key *)(base + L.lvl_off[c][l]);
         v->ids[c] = (const uint32_t *)(base + L.ids_off[c]);
         v->sub[c] = (const Key *)(base + L.sub_off[c]);
+        v->sub2[c] = (const Key *)(base + L.sub2_off[c]);
     }
     return HC_OK;
 }

@@ -31,6 +31,8 @@ struct IndexView {
     const Key *lvl[kMaxCurves][kMaxLevels + 1];   // lvl[c][0] = sorted keys
     uint64_t len_sub;                         // entries of sub (0 when levels == 0)
     const Key *sub[kMaxCurves];               // every kSub-th key of curve c
+    uint64_t len_sub2;                        // entries of sub2 (0 when levels < 2)
+    const Key *sub2[kMaxCurves];              // every (kFan kSub)-th key of curve c
     const uint32_t *ids[kMaxCurves];
     uint16_t perm[kMaxCurves * kDpc];
     uint32_t identity;                        // perm is 16c + j
@@ -58,14 +60,15 @@ namespace hc {
 
 // Layout of the index buffer: per curve, keys[n], ids[n], levels 1..D (level
 // L holds every 64^L-th key), then, when D >= 1, sub[ceil(n / 8)] (every 8th
-// key); every array starts on a 256-byte boundary.
+// key) and, when D >= 2, sub2[ceil(n / 512)] (every 512th key); every array
+// starts on a 256-byte boundary.
 struct Layout {
     uint32_t levels;
     uint64_t len[kMaxLevels + 1];
-    uint64_t len_sub;
+    uint64_t len_sub, len_sub2;
     size_t keys_off[kMaxCurves], ids_off[kMaxCurves];
     size_t lvl_off[kMaxCurves][kMaxLevels + 1];
-    size_t sub_off[kMaxCurves];
+    size_t sub_off[kMaxCurves], sub2_off[kMaxCurves];
     size_t total;
 };
 
@@ -82,6 +85,7 @@ inline Layout make_layout(uint32_t curves, uint64_t n)
     }
     L.levels = D;
     L.len_sub = D ? (n + kSub - 1) / kSub : 0;
+    L.len_sub2 = D >= 2 ? (n + kFan * kSub - 1) / (kFan * kSub) : 0;
     size_t off = 0;
     for (uint32_t c = 0; c < curves; c++) {
         L.keys_off[c] = off;
@@ -95,6 +99,8 @@ inline Layout make_layout(uint32_t curves, uint64_t n)
         }
         L.sub_off[c] = off;
         off = align256(off + sizeof(Key) * L.len_sub);
+        L.sub2_off[c] = off;
+        off = align256(off + sizeof(Key) * L.len_sub2);
     }
     L.total = off;
     return L;
