@@ -137,13 +137,19 @@ class Index:
             self.handle = None
 
     # -- helpers --------------------------------------------------------------
-    def scratch(self, nq, k_max=16):
-        """The index's shared scratch, grown to hold a batch of nq queries with
-        k up to k_max on either path (hc_search_scratch_bytes_k)."""
+    def scratch_bytes(self, nq, k_max=16):
+        """Scratch bytes of a batch of nq queries with k up to k_max on either
+        path (hc_search_scratch_bytes_k)."""
         sz = ct.c_size_t()
         capi.call("hc_search_scratch_bytes_k", self.handle, nq, int(k_max), ct.byref(sz))
-        if self._scratch is None or self._scratch.numel() < sz.value:
-            self._scratch = _empty_bytes(sz.value, self.db.device)
+        return sz.value
+
+    def scratch(self, nq, k_max=16):
+        """The index's shared scratch, grown to hold a batch of nq queries with
+        k up to k_max on either path."""
+        nb = self.scratch_bytes(nq, k_max)
+        if self._scratch is None or self._scratch.numel() < nb:
+            self._scratch = _empty_bytes(nb, self.db.device)
         return self._scratch
 
     def path(self, nq, k, w, scratch_bytes=None):
@@ -157,9 +163,7 @@ class Index:
 
     def new_scratch(self, nq, k_max=16):
         """A scratch buffer of its own (for concurrent streams)."""
-        sz = ct.c_size_t()
-        capi.call("hc_search_scratch_bytes_k", self.handle, nq, int(k_max), ct.byref(sz))
-        return _empty_bytes(sz.value, self.db.device)
+        return _empty_bytes(self.scratch_bytes(nq, k_max), self.db.device)
 
     def curve(self, c):
         """(keys int64 (n, 2) of {hi, lo}, ids int32 (n,)) views of curve c's list."""
@@ -216,11 +220,14 @@ class Index:
                   int(path), _stream())
         return ids, dists
 
-    def uneven_scratch(self, nq, k_stride, cfg=None):
+    def uneven_scratch_bytes(self, nq, k_stride, cfg=None):
         sz = ct.c_size_t()
         capi.call("hc_uneven_scratch_bytes", self.handle, nq, k_stride,
                   ct.byref(cfg) if cfg is not None else None, ct.byref(sz))
-        return _empty_bytes(sz.value, self.db.device)
+        return sz.value
+
+    def uneven_scratch(self, nq, k_stride, cfg=None):
+        return _empty_bytes(self.uneven_scratch_bytes(nq, k_stride, cfg), self.db.device)
 
     def search_uneven(self, queries, w=0, k=10, w_per_query=None, k_per_query=None,
                       k_stride=None, cfg=None, out=None, scratch=None):

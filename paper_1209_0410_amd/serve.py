@@ -46,55 +46,105 @@ def sinusoidal_arrivals(duration_s, lo_qps, hi_qps, period_s, seed):
     return t[keep]
 
 
+def _align(nbytes):
+    return (int(nbytes) + 255) & ~255
+
+
 class HbmBudget:
-    """Device bytes the in-flight batches may hold (admission control)."""
+    """The device memory of the batches in flight (admission control): one
+    buffer of `budget` bytes, allocated once when a Server binds it, from which
+    each batch takes a block at admission (its inputs, outputs, features, w
+    and search scratch) and returns it when the batch is done.  With
+    budget_bytes None the budget is the device's free memory less
+    reserve_bytes, read before the buffer exists; the Server caps it at what
+    its slots can use at once."""
 
     def __init__(self, budget_bytes=None, reserve_bytes=2 << 30):
         if budget_bytes is None:
             free, _ = torch.cuda.mem_get_info()
             budget_bytes = max(0, free - reserve_bytes)
-        self.budget = int(budget_bytes)
+        self.budget = int(budget_bytes) & ~255
         self.used = 0
         self.peak = 0
         self.refused = 0
+        self.buf = None
+        self._free = []             # free blocks (offset, bytes), by offset
+
+    def bind(self, device, cap_bytes):
+        """Allocates the buffer, of the budget or cap_bytes if that is less."""
+        if self.buf is None:
+            self.budget = min(self.budget, _align(cap_bytes))
+            self.buf = _device_bytes(self.budget, device)
+            self._free = [(0, self.budget)] if self.budget else []
+        return self
+
+    def largest(self):
+        """Bytes of the largest free block."""
+        return max((b for _, b in self._free), default=0)
 
     def take(self, nbytes):
-        if self.used + nbytes > self.budget:
-            return False
-        self.used += nbytes
-        self.peak = max(self.peak, self.used)
-        return True
+        """Offset of a block of nbytes (the first free one that fits), or None."""
+        nbytes = _align(nbytes)
+        for i, (o, b) in enumerate(self._free):
+            if b >= nbytes:
+                if b == nbytes:
+                    del self._free[i]
+                else:
+                    self._free[i] = (o + nbytes, b - nbytes)
+                self.used += nbytes
+                self.peak = max(self.peak, self.used)
+                return o
+        return None
 
-    def give(self, nbytes):
+    def give(self, off, nbytes):
+        """Returns the block taken at off (merged with free neighbours)."""
+        nbytes = _align(nbytes)
         self.used -= nbytes
+        merged = []
+        for o, b in sorted(self._free + [(off, nbytes)]):
+            if merged and merged[-1][0] + merged[-1][1] == o:
+                merged[-1] = (merged[-1][0], merged[-1][1] + b)
+            else:
+                merged.append((o, b))
+        self._free = merged
+
+
+def _device_bytes(nbytes, device):
+    """A 256-byte-aligned device buffer of nbytes."""
+    t = torch.empty(_align(nbytes) + 256, dtype=torch.uint8, device=device)
+    off = (-t.data_ptr()) % 256
+    return t[off:off + _align(nbytes)]
 
 
 class _Slot:
-    """One stream's buffers.  A batch of nq requests travels in one copy each
+    """One stream, its host buffers and, while a batch runs on it, views of
+    the batch's device block.  A batch of nq requests travels in one copy each
     way: in, the rows, k and the model's k' packed as [nq x 128 | nq | nq]
     (136 B per request); out, the ids then the distances, nq x k_stride each."""
     IN_BYTES = 136
 
-    def __init__(self, ix, cap, k_stride, dev, cfg, route="uneven"):
+    def __init__(self, cap, k_stride, dev):
         self.stream = torch.cuda.Stream(device=dev)
         self.k_stride = k_stride
-        self.d_in = torch.empty(cap * self.IN_BYTES, dtype=torch.uint8, device=dev)
         self.h_in = torch.empty(cap * self.IN_BYTES, dtype=torch.uint8).pin_memory()
-        self.w = torch.empty(cap, dtype=torch.int32, device=dev)
-        self.feat = torch.empty((cap, learned.FEATURES), dtype=torch.float32, device=dev)
-        self.d_out = torch.empty(2 * cap * k_stride, dtype=torch.int32, device=dev)
         self.h_out = torch.empty(2 * cap * k_stride, dtype=torch.int32).pin_memory()
-        self.fscratch = ix.new_scratch(cap)
-        if route == "uneven":
-            self.scratch = ix.uneven_scratch(cap, k_stride, cfg)
-        else:
-            # one search per k class on the automatic path: the scratch of
-            # either path for k up to k_stride (banded two passes for k > 16)
-            self.scratch = ix.new_scratch(cap, k_stride)
         self.classes = None          # batch route: (k, first, count) per class
         self.perm = None             # batch route: packed position -> request
         self.done = torch.cuda.Event()
         self.busy = False
+
+    def bind(self, buf, off, layout, nq):
+        """Views of a batch's buffers in the block of buf at off."""
+        def part(name, dtype):
+            o, nb = layout[name]
+            return buf[off + o:off + o + nb].view(dtype)
+        self.d_in = part("d_in", torch.uint8)
+        self.d_out = part("d_out", torch.int32)
+        self.scratch = part("scratch", torch.uint8)
+        if "w" in layout:
+            self.w = part("w", torch.int32)
+            self.feat = part("feat", torch.float32).view(nq, learned.FEATURES)
+            self.fscratch = part("fscratch", torch.uint8)
 
     def inputs(self, nq):
         """Device views (rows, k, k') of a batch of nq in d_in."""
@@ -109,13 +159,6 @@ class _Slot:
         b = (self.h_out if host else self.d_out)[:2 * nq * self.k_stride]
         m = nq * self.k_stride
         return b[:m].view(nq, self.k_stride), b[m:].view(nq, self.k_stride)
-
-
-def batch_bytes(nq, k_stride, curves=8, max_split=32):
-    """Device bytes one batch of nq requests needs beyond the resident index
-    on the uneven route (input, features, w, outputs, item scratch)."""
-    return nq * (128 + 8 + 4 * learned.FEATURES + 8 * k_stride +
-                 16 * curves + 4 * curves + 4 + 8 * max_split * k_stride)
 
 
 class Server:
@@ -158,9 +201,10 @@ class Server:
         self.band_min = int(band_min)
         self.max_wait_s = float(max_wait_s)
         dev = ix.db.device
-        self.slots = [_Slot(ix, self.max_batch, self.k_stride, dev, cfg, route)
-                      for _ in range(slots)]
+        self._layouts = {}
+        self.slots = [_Slot(self.max_batch, self.k_stride, dev) for _ in range(slots)]
         self.budget = budget if budget is not None else HbmBudget()
+        self.budget.bind(dev, slots * self.batch_bytes(self.max_batch))
 
     def _launch(self, slot, hq, hk, hkf, lo, hi):
         if self.route == "batch":
@@ -197,12 +241,43 @@ class Server:
             slot.done.record(slot.stream)
         slot.busy = True
 
-    def _bytes(self, nq):
-        """Device bytes charged to the budget for a batch of nq requests."""
-        if self.route == "uneven":
-            return batch_bytes(nq, self.k_stride)
-        # input, features, w and outputs; the search scratch is the slot's
-        return nq * (_Slot.IN_BYTES + 4 * learned.FEATURES + 4 + 8 * self.k_stride)
+    def _layout(self, nq):
+        """(name -> (offset, bytes), total) of a batch's device block: the
+        input, the outputs, the search scratch and, with a model, the w, the
+        features and their scratch; every part 256-byte aligned."""
+        if nq not in self._layouts:
+            if self.route == "uneven":
+                sb = self.ix.uneven_scratch_bytes(nq, self.k_stride, self.cfg)
+            else:
+                # one search per k class on the automatic path: the scratch of
+                # either path for k up to k_stride (banded two passes for k > 16)
+                sb = self.ix.scratch_bytes(nq, self.k_stride)
+            parts = [("d_in", nq * _Slot.IN_BYTES), ("d_out", 8 * nq * self.k_stride),
+                     ("scratch", sb)]
+            if self.model is not None:
+                parts += [("w", 4 * nq), ("feat", 4 * nq * learned.FEATURES),
+                          ("fscratch", self.ix.scratch_bytes(nq))]
+            lay, off = {}, 0
+            for name, nb in parts:
+                lay[name] = (off, nb)
+                off += _align(nb)
+            self._layouts[nq] = (lay, off)
+        return self._layouts[nq]
+
+    def batch_bytes(self, nq):
+        """Device bytes a batch of nq requests takes from the budget."""
+        return self._layout(nq)[1]
+
+    def _fit(self, avail, want):
+        """The largest batch (at most want requests) whose block fits avail bytes."""
+        lo, hi = 0, int(want)
+        while lo < hi:
+            mid = (lo + hi + 1) // 2
+            if self.batch_bytes(mid) <= avail:
+                lo = mid
+            else:
+                hi = mid - 1
+        return lo
 
     def _launch_batch(self, slot, hq, hk, hkf, lo, hi):
         """The batch route: requests packed by k (stable), one copy in, the
@@ -281,7 +356,7 @@ class Server:
         done_at = np.zeros(R)
         res_ids = np.zeros((R, self.k_stride), np.uint32) if keep_results else None
         res_d = np.zeros((R, self.k_stride), np.uint32) if keep_results else None
-        inflight = collections.deque()      # (slot, lo, hi, bytes)
+        inflight = collections.deque()      # (slot, lo, hi, block offset, bytes)
         cpu_inflight = []                    # futures of host-core requests
         pool = ThreadPoolExecutor(self.cpu_workers) if self.cpu_workers else None
         nxt = 0
@@ -316,7 +391,7 @@ class Server:
                 cpu_inflight = still
             # retire finished batches (oldest first; each slot records one event)
             for _ in range(len(inflight)):
-                slot, lo, hi, nb = inflight[0]
+                slot, lo, hi, boff, nb = inflight[0]
                 if not slot.done.query():
                     inflight.rotate(-1)
                     continue
@@ -330,7 +405,7 @@ class Server:
                     res_ids[lo:hi] = hids.numpy().view(np.uint32)
                     res_d[lo:hi] = hd.numpy().view(np.uint32)
                 slot.busy = False
-                self.budget.give(nb)
+                self.budget.give(boff, nb)
             if log is not None and realtime and now >= next_log:
                 log(f"t={now:.1f}s: {nxt} of {R} admitted, {len(inflight)} batches in flight")
                 next_log += 5.0
@@ -353,15 +428,16 @@ class Server:
                     and arrived < R and now - arrivals[nxt] < self.max_wait_s):
                 ready_end = nxt
             if ready_end > nxt and free:
-                per = self._bytes(1)
-                fit = (self.budget.budget - self.budget.used) // per
+                fit = self._fit(self.budget.largest(), ready_end - nxt)
                 if fit < 1 and not inflight:
                     raise RuntimeError("HBM budget is below one request's device memory")
-                end = min(ready_end, nxt + int(fit))
-                if end > nxt and self.budget.take(self._bytes(end - nxt)):
-                    nb = self._bytes(end - nxt)
+                if fit >= 1:
+                    end = nxt + fit
+                    lay, nb = self._layout(fit)
+                    boff = self.budget.take(nb)
+                    free[0].bind(self.budget.buf, boff, lay, fit)
                     self._launch(free[0], hq, hk, hkf, nxt, end)
-                    inflight.append((free[0], nxt, end, nb))
+                    inflight.append((free[0], nxt, end, boff, nb))
                     sizes.append(end - nxt)
                     batches += 1
                     nxt = end

@@ -61,15 +61,17 @@ def test_results_equal_alone_and_in_the_mix(env):
 
 
 def test_tight_hbm_budget_limits_batches(env):
-    from paper_1209_0410_amd.serve import HbmBudget, Server, batch_bytes
+    from paper_1209_0410_amd.serve import HbmBudget, Server
     R = 1500
     arr = np.zeros(R)                       # everything arrives at once
-    budget = HbmBudget(batch_bytes(200, 100))
-    srv = Server(env["gix"], w_fixed=16, k_stride=100, max_batch=1024, slots=3, budget=budget)
-    stats, (ids, d) = srv.run(arr, env["q"][:R], env["ks"][:R])
-    assert stats["max_batch"] <= 200 and budget.peak <= budget.budget
-    assert stats["admission_waits"] > 0
     srv2 = Server(env["gix"], w_fixed=16, k_stride=100, max_batch=1024, slots=1)
+    budget = HbmBudget(srv2.batch_bytes(200))
+    srv = Server(env["gix"], w_fixed=16, k_stride=100, max_batch=1024, slots=3, budget=budget)
+    assert budget.buf.numel() == budget.budget == srv.batch_bytes(200)
+    stats, (ids, d) = srv.run(arr, env["q"][:R], env["ks"][:R])
+    assert stats["max_batch"] == 200 and budget.peak <= budget.budget
+    assert budget.used == 0 and budget.largest() == budget.budget
+    assert stats["admission_waits"] > 0
     _, (ids2, d2) = srv2.run(arr, env["q"][:R], env["ks"][:R])
     assert (ids == ids2).all() and (d == d2).all()
 

@@ -1,4 +1,5 @@
-"""Host-side parts of the request loop (no GPU): the seeded arrival process."""
+"""Host-side parts of the request loop (no GPU): the seeded arrival process,
+the batch route's unpacking and the blocks of the device-memory budget."""
 import numpy as np
 
 
@@ -52,3 +53,25 @@ def test_batch_route_unpacks_k_classes():
         assert (res_d[r, :kv] == r + np.arange(kv)).all()
         assert (res_i[r, kv:] == 0xFFFFFFFF).all() and (res_d[r, kv:] == 0xFFFFFFFF).all()
     assert (res_i[:lo] == 0).all()
+
+
+def test_budget_blocks_first_fit_and_merge():
+    """The serving budget hands out 256-byte-aligned blocks of one buffer,
+    first fit, and merges returned blocks with free neighbours."""
+    import torch
+    from paper_1209_0410_amd.serve import HbmBudget
+    b = HbmBudget(4096 + 100).bind(torch.device("cpu"), 1 << 20)
+    assert b.budget == 4096 and b.buf.numel() == 4096 and b.buf.data_ptr() % 256 == 0
+    a = b.take(1000)                        # 1024 bytes
+    c = b.take(1024)
+    d = b.take(2048)
+    assert (a, c, d) == (0, 1024, 2048) and b.used == 4096 and b.largest() == 0
+    assert b.take(1) is None
+    b.give(c, 1024)
+    assert b.largest() == 1024 and b.take(1025) is None
+    b.give(a, 1000)                         # merges with the block at 1024
+    assert b.largest() == 2048 and b.take(2048) == 0
+    b.give(0, 2048)
+    b.give(d, 2048)
+    assert b.used == 0 and b.largest() == 4096 and b.peak == 4096
+    assert HbmBudget(1 << 30).bind(torch.device("cpu"), 5000).budget == 5120
