@@ -35,6 +35,9 @@ constexpr int kBandK = 16;        // longest list kept per query and curve
 constexpr uint32_t kMaxSplit = 4; // blocks a group's union may be split over
 constexpr uint64_t kBandFillBlocks = 512;   // blocks that fill MI355X (2 per CU)
 constexpr uint32_t kMQ = 32;             // queries per wavefront
+// a large batch's last round: the query slots whose groups may be dealt out
+// (at most half the resident blocks of 256 queries, or of 128 at 4 blocks per CU)
+constexpr uint32_t kTailQ = 65536;
 
 struct BandArgs {
     IndexView v;
@@ -59,6 +62,10 @@ struct BandArgs {
     uint32_t *redo;
     uint32_t tight;       // first pass: a half also drops pairs above the other half's 16th
     uint32_t split;       // row-store kernel: blocks per group (the union's tiles dealt out)
+    uint32_t split_from;  // groups (curve-major) below it take one block each
+    uint32_t pstride;     // lists per query and curve in partial (split, or 1 with a tail)
+    uint64_t *tail;       // lists of the dealt-out groups when split_from > 0:
+                          // [group - split_from][split][query of the group][k]
 };
 
 constexpr uint32_t kBandCap = 1024;   // k > 16: pairs collected per query (buffer entries)
@@ -76,7 +83,7 @@ inline uint32_t band_split(uint32_t curves, uint32_t nq, uint32_t block_q)
 }
 
 struct BandLayout {
-    size_t qkeys, pos, counts, order, partial, bound, theta, cnt, redo, buf, total;
+    size_t qkeys, pos, counts, order, partial, tail, bound, theta, cnt, redo, buf, total;
     uint32_t nbuckets;
 };
 
@@ -100,6 +107,10 @@ inline BandLayout band_layout(uint32_t curves, uint64_t n, uint32_t nq, uint32_t
     L.partial = off;
     off = align256(off + sizeof(uint64_t) * (size_t)nq * curves * band_split(curves, nq, 256) *
                          (two ? 2 * kBandK : kBandK));
+    L.tail = off;
+    if (!two)
+        off = align256(off + sizeof(uint64_t) * std::min<size_t>((size_t)nq * curves, kTailQ) *
+                             kMaxSplit * kBandK);
     L.bound = off;
     off = align256(off + sizeof(uint32_t) * (size_t)nq);
     L.theta = L.cnt = L.redo = L.buf = 0;
@@ -584,8 +595,10 @@ __device__ inline void unroll_blocks(F &f)
 //               key is appended to the query's buffer (second pass for k > 16).
 constexpr int kBandLists = 0, kBandHalves = 1, kBandThresh = 2;
 
-// SPLIT: each group's union is dealt out over a.split blocks (small batches);
-// without it the block decomposition folds to one block per group.
+// SPLIT: the union of each group from a.split_from on (curve-major; all of
+// them in a small batch, the last round's in a large one) is dealt out over
+// a.split blocks; without it the block decomposition folds to one block per
+// group.
 template <int KR, int NW, int MODE, bool SPLIT>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(KR > 10 ? 3 : 4)))
 void k_band_dma(BandArgs a)
@@ -606,9 +619,12 @@ void k_band_dma(BandArgs a)
     // curve-major; the split blocks of a group are neighbours and take the
     // tiles of its union in turn (tile i of the middle-out order to block
     // i mod split), so each sees every wavefront busy about as often
-    const uint32_t nsplit = SPLIT ? a.split : 1u, per_c = groups * nsplit;
-    const uint32_t c = blockIdx.x / per_c, grp = (blockIdx.x % per_c) / nsplit,
-                   sub = SPLIT ? blockIdx.x % nsplit : 0u;
+    const uint32_t S = SPLIT ? a.split : 1u, F = SPLIT ? a.split_from : 0u;
+    const uint32_t bid = blockIdx.x;
+    const bool whole = bid < F;
+    const uint32_t pair = whole ? bid : F + (bid - F) / S;
+    const uint32_t nsplit = whole ? 1u : S, sub = whole ? 0u : (bid - F) % S;
+    const uint32_t c = pair / groups, grp = pair % groups;
 
     const uint64_t slot = (uint64_t)grp * kBlockQ + (uint64_t)wv * kMQ + qn;
     const bool live = slot < a.nq;
@@ -887,7 +903,7 @@ void k_band_dma(BandArgs a)
     if (MODE == kBandHalves) {
         // both halves' lists: entries [16 h, 16 h + 16) of the query's 32 for curve c
         if (live) {
-            uint64_t *out = a.partial + (((uint64_t)q * C + c) * nsplit + sub) * (2 * kBandK) +
+            uint64_t *out = a.partial + (((uint64_t)q * C + c) * a.pstride + sub) * (2 * kBandK) +
                             kBandK * h;
 #pragma unroll
             for (int i = 0; i < KR; i++) out[i] = L[i];
@@ -928,7 +944,11 @@ void k_band_dma(BandArgs a)
         }
     }
     if (live && h == 0) {
-        uint64_t *out = a.partial + (((uint64_t)q * C + c) * nsplit + sub) * a.k;
+        // a dealt-out group of a large batch's last round: its own lists,
+        // merged by k_band_tail_merge
+        uint64_t *out = (SPLIT && a.tail && !whole)
+            ? a.tail + ((uint64_t)((pair - F) * S + sub) * kBlockQ + (slot - (uint64_t)grp * kBlockQ)) * a.k
+            : a.partial + (((uint64_t)q * C + c) * a.pstride + sub) * a.k;
         uint64_t kth = kNone;
 #pragma unroll
         for (int i = 0; i < KR; i++) {
@@ -952,7 +972,7 @@ __global__ __launch_bounds__(64 * kMergeWaves) void k_band_merge(BandArgs a)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint32_t q = blockIdx.x * kMergeWaves + wv;
     if (q >= a.nq) return;                 // the whole wavefront; no barrier follows
-    const uint32_t C = a.v.curves * a.split, k = a.k;     // lists: per curve and split block
+    const uint32_t C = a.v.curves * a.pstride, k = a.k;   // lists: per curve and split block
     const uint32_t nkeys = C * k;
     const uint64_t *src = a.partial + (uint64_t)q * nkeys;
     uint64_t *ls = lists[wv];
@@ -982,6 +1002,48 @@ __global__ __launch_bounds__(64 * kMergeWaves) void k_band_merge(BandArgs a)
     }
 }
 
+// A large batch's last round, after the main kernel: one thread per query
+// slot of a dealt-out group merges the group's split lists for that query
+// into its list for the curve.  The split blocks took disjoint tiles of the
+// curve's union, so the lists hold distinct ids and the merge keeps the k
+// smallest heads.
+__global__ __launch_bounds__(256) void k_band_tail_merge(BandArgs a, uint32_t block_q,
+                                                         uint64_t nslots)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nslots) return;
+    const uint32_t S = a.split, k = a.k, C = a.v.curves;
+    const uint32_t groups = (a.nq + block_q - 1) / block_q;
+    const uint32_t tp = (uint32_t)(t / block_q), i = (uint32_t)(t % block_q);
+    const uint32_t pair = a.split_from + tp, c = pair / groups, grp = pair % groups;
+    const uint64_t slot = (uint64_t)grp * block_q + i;
+    if (slot >= a.nq) return;
+    const uint32_t q = a.order[(uint64_t)c * a.nq + slot];
+    const uint64_t *src = a.tail + ((uint64_t)tp * S * block_q + i) * k;
+    const uint64_t sstep = (uint64_t)block_q * k;      // from one split list to the next
+    uint32_t hd[kMaxSplit];
+    uint64_t key[kMaxSplit];
+#pragma unroll
+    for (uint32_t s = 0; s < kMaxSplit; s++) {
+        hd[s] = 0;
+        key[s] = s < S ? src[s * sstep] : kNone;
+    }
+    uint64_t *out = a.partial + ((uint64_t)q * C + c) * k;
+    for (uint32_t j = 0; j < k; j++) {
+        uint64_t m = key[0];
+#pragma unroll
+        for (uint32_t s = 1; s < kMaxSplit; s++) m = key[s] < m ? key[s] : m;
+        out[j] = m;
+#pragma unroll
+        for (uint32_t s = 0; s < kMaxSplit; s++) {
+            if (key[s] == m && m != kNone) {
+                hd[s]++;
+                key[s] = hd[s] < k ? src[s * sstep + hd[s]] : kNone;
+            }
+        }
+    }
+}
+
 // k > 16, between the passes: one wavefront per query takes the k nearest
 // distinct keys among the first pass's 32 C candidates (all members of the
 // query's union), and the k-th of them is the threshold: the union's k
@@ -992,7 +1054,7 @@ __global__ __launch_bounds__(64) void k_band_theta(BandArgs a)
     __shared__ TopKShared sh;
     const int lane = threadIdx.x;
     const uint32_t q = blockIdx.x;
-    const uint32_t m = a.v.curves * a.split * 2 * kBandK;
+    const uint32_t m = a.v.curves * a.pstride * 2 * kBandK;
     const uint64_t *src = a.partial + (uint64_t)q * m;
     WaveTopK<0> tk;
     tk.init(a.k, &sh, lane);
@@ -1120,6 +1182,23 @@ static void launch_dma_lists(uint32_t k, dim3 grid, dim3 block, const BandArgs &
     else hipLaunchKernelGGL((k_band_dma<kBandK, NW, kBandLists, SPLIT>), grid, block, 0, st, a);
 }
 
+// Blocks of the row-store kernel for k that are resident on the device at
+// once (compute units x blocks per unit); 0 if the runtime cannot say.
+template <int NW>
+static uint64_t band_resident(uint32_t k)
+{
+    const void *f = k == 1    ? reinterpret_cast<const void *>(&k_band_dma<1, NW, kBandLists, true>)
+                    : k <= 4  ? reinterpret_cast<const void *>(&k_band_dma<4, NW, kBandLists, true>)
+                    : k <= 10 ? reinterpret_cast<const void *>(&k_band_dma<10, NW, kBandLists, true>)
+                              : reinterpret_cast<const void *>(&k_band_dma<kBandK, NW, kBandLists, true>);
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, 64 * NW, 0) != hipSuccess)
+        return 0;
+    return (uint64_t)cus * (uint64_t)per;
+}
+
 template <int NW>
 static void launch_band(const IndexView &v, uint32_t k, uint32_t nq, const BandArgs &a,
                         hipStream_t st)
@@ -1127,7 +1206,7 @@ static void launch_band(const IndexView &v, uint32_t k, uint32_t nq, const BandA
     const uint32_t blocks = (uint32_t)(((uint64_t)nq + NW * kMQ - 1) / (NW * kMQ)) * v.curves;
     const dim3 block(64 * NW);
     if (v.rows[0]) {
-        const dim3 grid(blocks * a.split);
+        const dim3 grid(a.split_from + (blocks - a.split_from) * a.split);
         if (a.split > 1) launch_dma_lists<NW, true>(k, grid, block, a, st);
         else launch_dma_lists<NW, false>(k, grid, block, a, st);
     } else {
@@ -1209,7 +1288,31 @@ hc_status band_search(const IndexView &v, const uint8_t *d_queries, uint32_t nq,
     // (one-pass searches only: in the first pass of k > 16 every block
     // builds its lists from nothing, so more blocks per group mean more
     // insertions)
-    a.split = (v.rows[0] && !two) ? band_split(v.curves, nq, band_block_q(w_fixed)) : 1u;
+    // A large batch ends with a partial round of blocks; when it is at most
+    // half a round, its groups are dealt out the same way (on the blocks that
+    // would stand idle) and their lists merged after the main kernel.
+    const uint32_t bq = band_block_q(w_fixed);
+    a.split = 1;
+    a.split_from = 0;
+    a.pstride = 1;
+    a.tail = nullptr;
+    uint64_t tail_slots = 0;
+    if (v.rows[0] && !two) {
+        const uint32_t sp = band_split(v.curves, nq, bq);
+        const uint64_t P = ((uint64_t)nq + bq - 1) / bq * v.curves;
+        const uint64_t res = sp > 1 ? 0 : bq == 4 * kMQ ? band_resident<4>(k) : band_resident<8>(k);
+        const uint64_t Lt = res ? P % res : 0;
+        if (sp > 1) {
+            a.split = sp;
+            a.pstride = sp;
+        } else if (P >= res && Lt > 0 && 2 * Lt <= res &&
+                   Lt * bq <= std::min<uint64_t>((uint64_t)nq * v.curves, kTailQ)) {
+            a.split = (uint32_t)std::min<uint64_t>(kMaxSplit, res / Lt);
+            a.split_from = (uint32_t)(P - Lt);
+            a.tail = (uint64_t *)(s + L.tail);
+            tail_slots = Lt * bq;
+        }
+    }
     const uint64_t nc = (uint64_t)v.curves * L.nbuckets;
     hipLaunchKernelGGL(k_band_fill, dim3((uint32_t)std::min<uint64_t>(4096, (nc + 255) / 256)),
                        dim3(256), 0, st, a.counts, nc, 0u);
@@ -1243,6 +1346,9 @@ hc_status band_search(const IndexView &v, const uint8_t *d_queries, uint32_t nq,
     else launch_band<8>(v, k, nq, a, st);
     rs = record_if(ev_end, st);
     if (rs != HC_OK) return rs;
+    if (tail_slots)
+        hipLaunchKernelGGL(k_band_tail_merge, dim3((uint32_t)((tail_slots + 255) / 256)),
+                           dim3(256), 0, st, a, bq, tail_slots);
     hipLaunchKernelGGL(k_band_merge, dim3((nq + kMergeWaves - 1) / kMergeWaves),
                        dim3(64 * kMergeWaves), 0, st, a);
     return last_hip();

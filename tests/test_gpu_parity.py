@@ -259,6 +259,32 @@ def test_rowstore_banded_bit_exact(c1, k, w):
     assert (u32(ids) == rid).all() and (u32(d) == rd).all()
 
 
+def test_rowstore_banded_last_round_split(c1, torch_mod):
+    """A batch whose banded grid ends with a short round: the last groups'
+    unions are dealt out over several blocks and their lists merged after the
+    main kernel.  With 256-query groups (w >= 8192) 18,176 queries make
+    71 x 8 = 568 groups, 56 past the 512 (k <= 10) or 256 (k = 16) blocks
+    resident at once on MI355X.  Every query's results equal the gather
+    kernel's, and the oracle's on a sample."""
+    from paper_1209_0410_amd import datagen
+    q = datagen.make_queries(18_176, seed=23)
+    gq = torch_mod.from_numpy(q).cuda()
+    gix = c1["gix"]
+    gix.attach_rowstore()
+    try:
+        for k in (1, 10, 16):
+            print(f"[last round] k={k}", flush=True)
+            ids, d = gix.search(gq, k, 9000, path=2)
+            gids, gd = gix.search(gq, k, 9000, path=1)
+            assert (u32(ids) == u32(gids)).all() and (u32(d) == u32(gd)).all(), k
+            if k == 10:
+                sample = np.arange(0, q.shape[0], 61)
+                rid, rd = c1["oix"].search(q[sample], k, 9000)
+                assert (u32(ids)[sample] == rid).all() and (u32(d)[sample] == rd).all()
+    finally:
+        gix.detach_rowstore()
+
+
 @pytest.mark.parametrize("n", [1, 65, 4097])
 def test_rowstore_small_shapes_and_per_query_w(oracle, torch_mod, n):
     from paper_1209_0410_amd import datagen
