@@ -194,6 +194,8 @@ hc_status hc_index_info(const hc_index *idx, uint64_t *n, uint32_t *curves);
  * hc_search_scratch_bytes_k: the same for k up to k_max (1..HC_K_MAX): with
  * 16 < k_max the banded path's two-pass buffers are included (k up to
  * HC_BAND_K_MAX, row store attached; about 8 KiB + 512 B x curves per query).
+ * Up to 4,096 queries it also holds the work items of a small batch's gather
+ * search (256 B x k_max per query; see HC_PATH_AUTO).
  * Errors: null pointers, k_max outside [1, HC_K_MAX] -> HC_ERR_INVALID. */
 hc_status hc_search_scratch_bytes(const hc_index *idx, uint32_t nq, size_t *bytes);
 hc_status hc_search_scratch_bytes_k(const hc_index *idx, uint32_t nq, uint32_t k_max,
@@ -269,7 +271,14 @@ hc_status hc_search_encoded(const hc_index *idx, const uint8_t *d_queries, uint3
  *                  batch makes at least 512 blocks (nq / 128 or nq / 256 per
  *                  curve, times curves), k <= 16 (or k <= HC_BAND_K_MAX with
  *                  the row store) and the scratch holds
- *                  hc_search_scratch_bytes_k for that k; else gather.
+ *                  hc_search_scratch_bytes_k for that k; else gather.  A
+ *                  gather search of a batch under a third of the device's
+ *                  resident gather wavefronts (and at most 4,096 queries),
+ *                  with 2 w curves >= 32,768 window slots per query and a
+ *                  scratch of hc_search_scratch_bytes_k for that k, runs as
+ *                  the work items of hc_search_uneven instead (each query's
+ *                  windows cut into pieces that many wavefronts stream at
+ *                  once, then merged); the results are the same.
  * hc_search_encoded is hc_search_encoded_ex with HC_PATH_AUTO. */
 #define HC_BAND_K_MAX 128u
 #define HC_PATH_AUTO 0u

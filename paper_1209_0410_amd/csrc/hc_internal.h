@@ -133,6 +133,20 @@ hc_status gather_search_only(const IndexView &v, const uint8_t *d_queries, const
                              const uint32_t *only, uint32_t *d_out_ids, uint32_t *d_out_dists,
                              hipStream_t st);
 
+// Work-item search (hc_uneven.hip): each query's windows cut into items that
+// the wavefronts of a persistent grid take from a queue, then merged.  With
+// keys_ready the query keys are already at the start of d_scratch.
+hc_status items_search(const IndexView &v, const uint8_t *d_queries, uint32_t nq,
+                       uint32_t w_fixed, const uint32_t *d_w, uint32_t k_fixed,
+                       const uint32_t *d_k, uint32_t k_stride, uint32_t *d_out_ids,
+                       uint32_t *d_out_dists, void *d_scratch, size_t scratch_bytes,
+                       uint32_t chunk, uint32_t max_split, uint32_t per_cu, bool keys_ready,
+                       hipStream_t st, hipEvent_t ev_begin, hipEvent_t ev_end);
+// its scratch with the default launch shape
+size_t items_scratch_bytes(uint32_t curves, uint32_t nq, uint32_t k_stride);
+constexpr uint32_t kItemChunk = 8192;   // default item size in window slots
+constexpr uint32_t kItemSplit = 32;     // default items per query at most
+
 // Banded search (hc_band.hip), query keys already at the start of d_scratch.
 // Scratch for a batch of nq queries with k up to k_max (k_max > 16 adds the
 // buffers of the two-pass search; it needs the row store).

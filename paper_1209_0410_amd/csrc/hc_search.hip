@@ -38,6 +38,7 @@ constexpr double kBandShare = 3.5;      // windows per list entry from which to 
 constexpr double kBandMinBlocks = 512;  // banded blocks from which to band (2 per CU)
                                         // (MI355X, n = 1e7, nq = 1e5: break-even at w ~ 512)
 constexpr uint32_t kMaxSetSlots = 4096; // union capacity of the set kernel
+constexpr uint32_t kItemsMaxQ = 4096;   // largest batch whose scratch holds the work items
 constexpr int kIdBatch = 16;            // set kernel: ids loaded before inserting
 
 struct SearchArgs {
@@ -224,6 +225,37 @@ static hc_status launch_stream(const SearchArgs &a, hipStream_t st)
 
 // A register list as long as k (1, 4, 10 or 16) for k <= 16, the LDS buffer
 // beyond.
+// Wavefronts of the gather kernel for k resident on the device at once
+// (compute units x wavefronts per unit; 0 if the runtime cannot say).
+static uint64_t gather_resident(uint32_t k)
+{
+    const void *f = k == 1    ? reinterpret_cast<const void *>(&k_stream<1, 1>)
+                    : k <= 4  ? reinterpret_cast<const void *>(&k_stream<4, 1>)
+                    : k <= 10 ? reinterpret_cast<const void *>(&k_stream<10, 1>)
+                    : k <= (uint32_t)kKR ? reinterpret_cast<const void *>(&k_stream<kKR, 1>)
+                                         : reinterpret_cast<const void *>(&k_stream<0, 1>);
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, 64, 0) != hipSuccess)
+        return 0;
+    return (uint64_t)cus * (uint64_t)per;
+}
+
+// A gather search of a batch too small to keep the device's memory busy with
+// one wavefront per query (under a third of the resident wavefronts) and of
+// long windows (at least 4 items of slots per query) runs as work items: each
+// query's windows are cut into pieces that many wavefronts stream at once,
+// then merged (measured on MI355X: 10^3 queries at N = 5e7, w = 125,952 take
+// 41.8 ms so, 68.0 ms with one wavefront per query).
+static bool items_route(const hc_index *idx, uint32_t nq, uint32_t k, uint64_t w,
+                        size_t scratch_bytes)
+{
+    if (2ull * w * idx->v.curves < 4ull * kItemChunk || nq > kItemsMaxQ) return false;
+    if (scratch_bytes < items_scratch_bytes(idx->v.curves, nq, k)) return false;
+    return 3ull * nq < gather_resident(k);
+}
+
 template <int G>
 static hc_status launch_search_g(const SearchArgs &a, hipStream_t st)
 {
@@ -339,6 +371,8 @@ hc_status hc_search_scratch_bytes_k(const hc_index *idx, uint32_t nq, uint32_t k
     const uint32_t kb = std::min<uint32_t>(k_max, kBandKMax);
     *bytes = std::max(align256(sizeof(Key) * (size_t)m * idx->v.curves),
                       band_scratch_bytes(idx->v.curves, idx->v.n, m, kb));
+    if (m <= kItemsMaxQ)   // a small batch may run as work items (the gather path)
+        *bytes = std::max(*bytes, items_scratch_bytes(idx->v.curves, m, k_max));
     return HC_OK;
 }
 
@@ -363,10 +397,15 @@ hc_status hc_search_encoded_ex(const hc_index *idx, const uint8_t *d_queries, ui
     if (st != HC_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     const uint64_t hint = d_w ? (w_fixed ? w_fixed : 64) : w_fixed;
-    if (path == HC_PATH_AUTO) hc_search_choose_path(idx, nq, k, (uint32_t)hint, scratch_bytes, &path);
+    const bool automatic = path == HC_PATH_AUTO;
+    if (automatic) hc_search_choose_path(idx, nq, k, (uint32_t)hint, scratch_bytes, &path);
     if (path == HC_PATH_BAND)
         return band_search(idx->v, d_queries, nq, k, w_fixed, d_w, d_out_ids, d_out_dists,
                            d_scratch, scratch_bytes, s, idx->kernel_begin, idx->kernel_end);
+    if (automatic && items_route(idx, nq, k, hint, scratch_bytes))
+        return items_search(idx->v, d_queries, nq, w_fixed, d_w, k, nullptr, k, d_out_ids,
+                            d_out_dists, d_scratch, scratch_bytes, kItemChunk, kItemSplit, 0,
+                            true, s, idx->kernel_begin, idx->kernel_end);
     SearchArgs a = base_args(idx, d_queries, nq, d_scratch);
     a.k = k;
     a.w_fixed = w_fixed;

@@ -250,9 +250,9 @@ static UnevenLayout uneven_layout(uint32_t curves, uint32_t nq, uint32_t k_strid
 static void resolve_cfg(const hc_uneven_cfg *cfg, uint32_t *chunk, uint32_t *max_split,
                         uint32_t *per_cu)
 {
-    *chunk = cfg && cfg->chunk_slots ? cfg->chunk_slots : 8192u;
+    *chunk = cfg && cfg->chunk_slots ? cfg->chunk_slots : kItemChunk;
     *chunk = (*chunk + 63) / 64 * 64;
-    *max_split = cfg && cfg->max_split ? cfg->max_split : 32u;
+    *max_split = cfg && cfg->max_split ? cfg->max_split : kItemSplit;
     *per_cu = cfg ? cfg->blocks_per_cu : 0u;
 }
 
@@ -280,6 +280,80 @@ static uint32_t persistent_blocks(uint32_t per_cu)
         cus_cache[dev] = cus;
     }
     return (uint32_t)cus * (per_cu ? per_cu : (uint32_t)occ);
+}
+
+// The work-item search of nq queries (arguments checked by the caller); with
+// keys_ready the query keys are already at the start of the scratch.  ev_begin
+// and ev_end, when set, are recorded around k_items.
+hc_status items_search(const IndexView &v, const uint8_t *d_queries, uint32_t nq,
+                       uint32_t w_fixed, const uint32_t *d_w, uint32_t k_fixed,
+                       const uint32_t *d_k, uint32_t k_stride, uint32_t *d_out_ids,
+                       uint32_t *d_out_dists, void *d_scratch, size_t scratch_bytes,
+                       uint32_t chunk, uint32_t max_split, uint32_t per_cu, bool keys_ready,
+                       hipStream_t st, hipEvent_t ev_begin, hipEvent_t ev_end)
+{
+    const UnevenLayout L = uneven_layout(v.curves, nq, k_stride, max_split);
+    if (scratch_bytes < L.total) return HC_ERR_SIZE;
+    if ((uint64_t)nq * max_split >= 0xFFFFFFFFull) return HC_ERR_UNSUPPORTED;
+
+    uint8_t *s = (uint8_t *)d_scratch;
+    UnevenArgs a;
+    memset(&a, 0, sizeof(a));
+    a.v = v;
+    a.queries = d_queries;
+    a.qkeys = (const Key *)(s + L.qkeys);
+    a.nq = nq;
+    a.d_w = d_w;
+    a.d_k = d_k;
+    a.w_fixed = w_fixed;
+    a.k_fixed = k_fixed;
+    a.k_stride = k_stride;
+    a.chunk = chunk;
+    a.max_split = max_split;
+    a.pos = (uint32_t *)(s + L.pos);
+    a.base = (uint32_t *)(s + L.base);
+    a.queue = (uint32_t *)(s + L.queue);
+    a.partial = (uint64_t *)(s + L.partial);
+    a.out_ids = d_out_ids;
+    a.out_dists = d_out_dists;
+
+    if (!keys_ready) {
+        const hc_status rc = encode_rows(a.v, d_queries, nq, (Key *)(s + L.qkeys), st);
+        if (rc != HC_OK) return rc;
+    }
+    hipLaunchKernelGGL(k_plan, dim3(nq), dim3(64), 0, st, a);
+    {   // item offsets: one block per 4,096 queries, then the tile sums
+        const uint64_t nb1 = (uint64_t)nq + 1;
+        const uint32_t tiles = (uint32_t)((nb1 + kScanTile - 1) / kScanTile);
+        uint32_t *sums = (uint32_t *)(s + L.sums);
+        hipLaunchKernelGGL(k_scan_tile_sums, dim3(tiles), dim3(kScanThreads), 0, st, a.base, nb1,
+                           sums);
+        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(kScanThreads), 0, st, sums,
+                           (uint64_t)tiles);
+        hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(kScanThreads), 0, st, a.base, nb1,
+                           (const uint32_t *)sums);
+    }
+    const bool big = k_stride > 16;
+    uint32_t blocks = big ? persistent_blocks<true>(per_cu) : persistent_blocks<false>(per_cu);
+    if (blocks == 0) return HC_ERR_HIP;
+    // a query has at most max_split items: a small batch needs no full grid
+    blocks = (uint32_t)std::min<uint64_t>(blocks, (uint64_t)nq * max_split);
+    hc_status rc = record_if(ev_begin, st);
+    if (rc != HC_OK) return rc;
+    if (big) hipLaunchKernelGGL(k_items<true>, dim3(blocks), dim3(64), 0, st, a);
+    else hipLaunchKernelGGL(k_items<false>, dim3(blocks), dim3(64), 0, st, a);
+    rc = record_if(ev_end, st);
+    if (rc != HC_OK) return rc;
+    if (big) hipLaunchKernelGGL(k_merge<true>, dim3(nq), dim3(64), 0, st, a);
+    else hipLaunchKernelGGL(k_merge<false>, dim3(nq), dim3(64), 0, st, a);
+    return last_hip();
+}
+
+size_t items_scratch_bytes(uint32_t curves, uint32_t nq, uint32_t k_stride)
+{
+    uint32_t chunk, max_split, per_cu;
+    resolve_cfg(nullptr, &chunk, &max_split, &per_cu);
+    return uneven_layout(curves, std::max<uint32_t>(nq, 1), k_stride, max_split).total;
 }
 
 }  // namespace hc
@@ -313,59 +387,9 @@ hc_status hc_search_uneven(const hc_index *idx, const uint8_t *d_queries, uint32
     uint32_t chunk, max_split, per_cu;
     resolve_cfg(cfg, &chunk, &max_split, &per_cu);
     if (chunk > (1u << 30) || max_split < 1 || max_split > 4096) return HC_ERR_INVALID;
-    const UnevenLayout L = uneven_layout(idx->v.curves, nq, k_stride, max_split);
-    if (scratch_bytes < L.total) return HC_ERR_SIZE;
-    if ((uint64_t)nq * max_split >= 0xFFFFFFFFull) return HC_ERR_UNSUPPORTED;
-
-    uint8_t *s = (uint8_t *)d_scratch;
-    UnevenArgs a;
-    memset(&a, 0, sizeof(a));
-    a.v = idx->v;
-    a.queries = d_queries;
-    a.qkeys = (const Key *)(s + L.qkeys);
-    a.nq = nq;
-    a.d_w = d_w;
-    a.d_k = d_k;
-    a.w_fixed = w_fixed;
-    a.k_fixed = k_fixed;
-    a.k_stride = k_stride;
-    a.chunk = chunk;
-    a.max_split = max_split;
-    a.pos = (uint32_t *)(s + L.pos);
-    a.base = (uint32_t *)(s + L.base);
-    a.queue = (uint32_t *)(s + L.queue);
-    a.partial = (uint64_t *)(s + L.partial);
-    a.out_ids = d_out_ids;
-    a.out_dists = d_out_dists;
-
-    hipStream_t st = (hipStream_t)stream;
-    hc_status rc = encode_rows(a.v, d_queries, nq, (Key *)(s + L.qkeys), st);
-    if (rc != HC_OK) return rc;
-    hipLaunchKernelGGL(k_plan, dim3(nq), dim3(64), 0, st, a);
-    {   // item offsets: one block per 4,096 queries, then the tile sums
-        const uint64_t nb1 = (uint64_t)nq + 1;
-        const uint32_t tiles = (uint32_t)((nb1 + kScanTile - 1) / kScanTile);
-        uint32_t *sums = (uint32_t *)(s + L.sums);
-        hipLaunchKernelGGL(k_scan_tile_sums, dim3(tiles), dim3(kScanThreads), 0, st, a.base, nb1,
-                           sums);
-        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(kScanThreads), 0, st, sums,
-                           (uint64_t)tiles);
-        hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(kScanThreads), 0, st, a.base, nb1,
-                           (const uint32_t *)sums);
-    }
-    const bool big = k_stride > 16;
-    uint32_t blocks = big ? persistent_blocks<true>(per_cu) : persistent_blocks<false>(per_cu);
-    if (blocks == 0) return HC_ERR_HIP;
-    // a query has at most max_split items: a small batch needs no full grid
-    blocks = (uint32_t)std::min<uint64_t>(blocks, (uint64_t)nq * max_split);
-    if (big) {
-        hipLaunchKernelGGL(k_items<true>, dim3(blocks), dim3(64), 0, st, a);
-        hipLaunchKernelGGL(k_merge<true>, dim3(nq), dim3(64), 0, st, a);
-    } else {
-        hipLaunchKernelGGL(k_items<false>, dim3(blocks), dim3(64), 0, st, a);
-        hipLaunchKernelGGL(k_merge<false>, dim3(nq), dim3(64), 0, st, a);
-    }
-    return last_hip();
+    return items_search(idx->v, d_queries, nq, w_fixed, d_w, k_fixed, d_k, k_stride, d_out_ids,
+                        d_out_dists, d_scratch, scratch_bytes, chunk, max_split, per_cu, false,
+                        (hipStream_t)stream, nullptr, nullptr);
 }
 
 }  // extern "C"

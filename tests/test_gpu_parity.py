@@ -259,6 +259,30 @@ def test_rowstore_banded_bit_exact(c1, k, w):
     assert (u32(ids) == rid).all() and (u32(d) == rd).all()
 
 
+@pytest.mark.parametrize("k", [1, 10, 100])
+def test_small_batch_long_windows_as_work_items(c1, torch_mod, k):
+    """A batch too small to keep the device busy with one wavefront per query,
+    at long windows (2 w x 8 curves >= 32,768 slots per query), runs as work
+    items on the automatic path.  Its results equal the gather kernel's
+    (forced path) on every query, with a fixed w and with a w per query, and
+    the oracle's at k = 10."""
+    gix = c1["gix"]
+    gq = c1["gq"][:200].contiguous()
+    print(f"[items] k={k}", flush=True)
+    ids, d = gix.search(gq, k, 3000)
+    gids, gd = gix.search(gq, k, 3000, path=1)
+    assert (u32(ids) == u32(gids)).all() and (u32(d) == u32(gd)).all()
+    g = torch_mod.Generator().manual_seed(29)
+    wq = torch_mod.randint(2100, 6000, (200,), generator=g, dtype=torch_mod.int32).cuda()
+    ids, d = gix.search(gq, k, 3000, w_per_query=wq)
+    gids, gd = gix.search(gq, k, 3000, w_per_query=wq, path=1)
+    assert (u32(ids) == u32(gids)).all() and (u32(d) == u32(gd)).all()
+    if k == 10:
+        rid, rd = c1["oix"].search(c1["q"][:200], k, 3000)
+        ids, d = gix.search(gq, k, 3000)
+        assert (u32(ids) == rid).all() and (u32(d) == rd).all()
+
+
 def test_rowstore_banded_last_round_split(c1, torch_mod):
     """A batch whose banded grid ends with a short round: the last groups'
     unions are dealt out over several blocks and their lists merged after the
