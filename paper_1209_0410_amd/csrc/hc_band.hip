@@ -1243,6 +1243,11 @@ uint64_t band_blocks(uint32_t curves, uint32_t nq, uint32_t w)
     return ((uint64_t)nq + q - 1) / q * curves;
 }
 
+uint64_t band_split_blocks(uint32_t curves, uint32_t nq, uint32_t w)
+{
+    return band_blocks(curves, nq, w) * band_split(curves, nq, band_block_q(w));
+}
+
 // Runs the banded search with the query keys already in d_scratch.  w_fixed
 // is the window, or with per-query windows a typical one (the block size
 // follows it).  ev_begin / ev_end (may be null) are recorded around the

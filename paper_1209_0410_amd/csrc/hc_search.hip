@@ -37,6 +37,10 @@ constexpr uint32_t kBandK16 = 16;       // k the banded path takes in one pass
 constexpr double kBandShare = 3.5;      // windows per list entry from which to band
 constexpr double kBandMinBlocks = 512;  // banded blocks from which to band (2 per CU)
                                         // (MI355X, n = 1e7, nq = 1e5: break-even at w ~ 512)
+constexpr double kBandMinSplit = 256;   // the same once a small batch's groups are dealt
+                                        // out (MI355X, recall-0.90 windows at n = 1e7 and
+                                        // 5e7: banded 2.4-4x faster than gather at 2,048
+                                        // queries; work items are faster at 1,000)
 constexpr uint32_t kMaxSetSlots = 4096; // union capacity of the set kernel
 constexpr uint32_t kItemsMaxQ = 4096;   // largest batch whose scratch holds the work items
 constexpr int kIdBatch = 16;            // set kernel: ids loaded before inserting
@@ -436,7 +440,10 @@ hc_status hc_search_choose_path(const hc_index *idx, uint32_t nq, uint32_t k, ui
     // batch makes enough blocks to fill the device (a small batch spreads each
     // block over a long stretch of the list, streamed by few blocks)
     const bool shared = 2.0 * (double)w * nq >= kBandShare * (double)idx->v.n;
-    const bool wide = (double)band_blocks(idx->v.curves, nq, w) >= kBandMinBlocks;
+    // one pass over the row store deals a small batch's groups out over more blocks
+    const bool split = idx->v.rows[0] && k <= kBandK16;
+    const bool wide = split ? (double)band_split_blocks(idx->v.curves, nq, w) >= kBandMinSplit
+                            : (double)band_blocks(idx->v.curves, nq, w) >= kBandMinBlocks;
     // k <= 16: one pass; 16 < k <= kBandKMax: two passes over the row store
     const bool k_ok = k >= 1 && (k <= kBandK16 || (k <= kBandKMax && idx->v.rows[0]));
     const bool fits = k_ok && scratch_bytes >= band_scratch_bytes(idx->v.curves, idx->v.n, nq, k);

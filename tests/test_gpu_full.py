@@ -50,7 +50,7 @@ def full(oracle):
 
 @pytest.mark.parametrize("w,path,k", [(W_RECALL90, PATH_BAND, K), (64, PATH_GATHER, K),
                                       (4096, PATH_BAND, K), (W_RECALL90, PATH_BAND, 1),
-                                      (W_RECALL90, PATH_BAND, 16)])
+                                      (W_RECALL90, PATH_BAND, 16), (64, PATH_GATHER, 100)])
 def test_full_size_sampled_rows_bit_exact(full, w, path, k):
     import torch
     gix, sc = full["gix"], full["sc"]
