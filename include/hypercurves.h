@@ -270,8 +270,8 @@ hc_status hc_search_encoded(const hc_index *idx, const uint8_t *d_queries, uint3
  *  HC_PATH_AUTO:   banded when 2 w nq >= 3.5 n (w = w_fixed or the hint), the
  *                  batch makes at least 512 blocks (nq / 128 or nq / 256 per
  *                  curve, times curves; with the row store at least 256,
- *                  counting for k <= 16 the blocks a small batch's groups
- *                  are dealt out over, up to 4 each), k <= 16 (or
+ *                  counting the blocks a small batch's groups are dealt out
+ *                  over, up to 4 each), k <= 16 (or
  *                  k <= HC_BAND_K_MAX with the row store) and the scratch holds
  *                  hc_search_scratch_bytes_k for that k; else gather.  A
  *                  gather search of a batch under a third of the device's

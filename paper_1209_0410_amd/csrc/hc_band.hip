@@ -72,11 +72,20 @@ constexpr uint32_t kBandCap = 1024;   // k > 16: pairs collected per query (buff
 constexpr uint32_t kBandTightK = 32;  // k > 16 up to this: the first pass's halves share a bound
 
 // Blocks a group's union is dealt out over: the least number that gives the
-// grid kBandFillBlocks blocks, at most kMaxSplit.  Larger groups give fewer
-// blocks, so the 256-query groups bound it for any window.
-inline uint32_t band_split(uint32_t curves, uint32_t nq, uint32_t block_q)
+// grid kBandFillBlocks blocks (two per CU), at most kMaxSplit.  Larger groups
+// give fewer blocks, so the 256-query groups bound it for any window.  The
+// two passes of k > 16 run one block per CU and split only a batch of fewer
+// than 256 groups: every split block builds its lists from nothing, which
+// costs more than the rounds it saves once the groups fill the device
+// (MI355X, N = 1e7, w = 27,648, k = 100: 8,192 queries in 256 blocks 31.4 ms,
+// split over 512 45.8 ms; 4,096 queries in 128 blocks 40.0 ms, split over 256
+// 31.7 ms, over 512 21.8 ms; N = 1e8, w = 241,664: 6,000 queries 213.8 ms,
+// split over 564 blocks 117.7 ms).
+inline uint32_t band_split(uint32_t curves, uint32_t nq, uint32_t block_q,
+                           uint32_t k = 1)
 {
     const uint64_t blocks = ((uint64_t)nq + block_q - 1) / block_q * curves;
+    if (k > (uint32_t)kBandK && blocks >= kBandFillBlocks / 2) return 1;
     uint32_t sp = 1;
     while (sp < kMaxSplit && blocks * sp < kBandFillBlocks) sp++;
     return sp;
@@ -1243,9 +1252,9 @@ uint64_t band_blocks(uint32_t curves, uint32_t nq, uint32_t w)
     return ((uint64_t)nq + q - 1) / q * curves;
 }
 
-uint64_t band_split_blocks(uint32_t curves, uint32_t nq, uint32_t w)
+uint64_t band_split_blocks(uint32_t curves, uint32_t nq, uint32_t w, uint32_t k)
 {
-    return band_blocks(curves, nq, w) * band_split(curves, nq, band_block_q(w));
+    return band_blocks(curves, nq, w) * band_split(curves, nq, band_block_q(w), k);
 }
 
 // Runs the banded search with the query keys already in d_scratch.  w_fixed
@@ -1288,11 +1297,8 @@ hc_status band_search(const IndexView &v, const uint8_t *d_queries, uint32_t nq,
         a.tight = k <= kBandTightK;
     }
     // a small batch makes few groups; over the row store each group's union
-    // is then dealt out over up to kMaxSplit blocks, so that the grid has
-    // at least kBandFillBlocks blocks (two per CU)
-    // (one-pass searches only: in the first pass of k > 16 every block
-    // builds its lists from nothing, so more blocks per group mean more
-    // insertions)
+    // is then dealt out over up to kMaxSplit blocks, so that the grid fills
+    // the device (band_split)
     // A large batch ends with a partial round of blocks; when it is at most
     // half a round, its groups are dealt out the same way (on the blocks that
     // would stand idle) and their lists merged after the main kernel.
@@ -1302,10 +1308,11 @@ hc_status band_search(const IndexView &v, const uint8_t *d_queries, uint32_t nq,
     a.pstride = 1;
     a.tail = nullptr;
     uint64_t tail_slots = 0;
-    if (v.rows[0] && !two) {
-        const uint32_t sp = band_split(v.curves, nq, bq);
+    if (v.rows[0]) {
+        const uint32_t sp = band_split(v.curves, nq, bq, k);
         const uint64_t P = ((uint64_t)nq + bq - 1) / bq * v.curves;
-        const uint64_t res = sp > 1 ? 0 : bq == 4 * kMQ ? band_resident<4>(k) : band_resident<8>(k);
+        const uint64_t res = sp > 1 || two ? 0
+                             : bq == 4 * kMQ ? band_resident<4>(k) : band_resident<8>(k);
         const uint64_t Lt = res ? P % res : 0;
         if (sp > 1) {
             a.split = sp;

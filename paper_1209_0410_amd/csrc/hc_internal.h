@@ -153,8 +153,8 @@ constexpr uint32_t kItemSplit = 32;     // default items per query at most
 size_t band_scratch_bytes(uint32_t curves, uint64_t n, uint32_t nq, uint32_t k_max);
 constexpr uint32_t kBandKMax = HC_BAND_K_MAX;   // largest k the banded path takes
 uint64_t band_blocks(uint32_t curves, uint32_t nq, uint32_t w);   // blocks of its main kernel
-// the same when a small batch's groups are dealt out (one pass, row store)
-uint64_t band_split_blocks(uint32_t curves, uint32_t nq, uint32_t w);
+// the same when a small batch's groups are dealt out (row store)
+uint64_t band_split_blocks(uint32_t curves, uint32_t nq, uint32_t w, uint32_t k);
 hc_status band_search(const IndexView &v, const uint8_t *d_queries, uint32_t nq, uint32_t k,
                       uint32_t w_fixed, const uint32_t *d_w, uint32_t *d_out_ids,
                       uint32_t *d_out_dists, void *d_scratch, size_t scratch_bytes,

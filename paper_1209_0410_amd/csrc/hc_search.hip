@@ -38,11 +38,10 @@ constexpr double kBandShare = 3.5;      // windows per list entry from which to 
 constexpr double kBandMinBlocks = 512;  // banded blocks from which to band (2 per CU)
                                         // (MI355X, n = 1e7, nq = 1e5: break-even at w ~ 512)
 constexpr double kBandMinRows = 256;    // the same over the row store, counting the blocks
-                                        // a small batch's groups are dealt out over (k <= 16)
+                                        // a small batch's groups are dealt out over
                                         // (MI355X, recall-0.90 windows at n = 1e7 and 5e7:
                                         // k = 10 bands 2.4-4x faster than gather at 2,048
-                                        // queries, work items are faster at 1,000; k = 100
-                                        // bands 2.2x faster at 8,192, gathers faster at 4,096)
+                                        // queries, work items are faster at 1,000)
 constexpr uint32_t kMaxSetSlots = 4096; // union capacity of the set kernel
 constexpr uint32_t kItemsMaxQ = 4096;   // largest batch whose scratch holds the work items
 constexpr int kIdBatch = 16;            // set kernel: ids loaded before inserting
@@ -442,11 +441,10 @@ hc_status hc_search_choose_path(const hc_index *idx, uint32_t nq, uint32_t k, ui
     // batch makes enough blocks to fill the device (a small batch spreads each
     // block over a long stretch of the list, streamed by few blocks)
     const bool shared = 2.0 * (double)w * nq >= kBandShare * (double)idx->v.n;
-    // over the row store one pass deals a small batch's groups out over more blocks
+    // over the row store a small batch's groups are dealt out over more blocks
     const bool rows = idx->v.rows[0] != nullptr;
-    const double blocks = rows && k <= kBandK16
-                              ? (double)band_split_blocks(idx->v.curves, nq, w)
-                              : (double)band_blocks(idx->v.curves, nq, w);
+    const double blocks = rows ? (double)band_split_blocks(idx->v.curves, nq, w, k)
+                               : (double)band_blocks(idx->v.curves, nq, w);
     const bool wide = blocks >= (rows ? kBandMinRows : kBandMinBlocks);
     // k <= 16: one pass; 16 < k <= kBandKMax: two passes over the row store
     const bool k_ok = k >= 1 && (k <= kBandK16 || (k <= kBandKMax && idx->v.rows[0]));
