@@ -1192,20 +1192,28 @@ static void launch_dma_lists(uint32_t k, dim3 grid, dim3 block, const BandArgs &
 }
 
 // Blocks of the row-store kernel for k that are resident on the device at
-// once (compute units x blocks per unit); 0 if the runtime cannot say.
+// once (compute units x blocks per unit); 0 if the runtime cannot say.  The
+// device queries run once per process, device and list length (a racing
+// repeat is harmless).
 template <int NW>
 static uint64_t band_resident(uint32_t k)
 {
-    const void *f = k == 1    ? reinterpret_cast<const void *>(&k_band_dma<1, NW, kBandLists, true>)
-                    : k <= 4  ? reinterpret_cast<const void *>(&k_band_dma<4, NW, kBandLists, true>)
-                    : k <= 10 ? reinterpret_cast<const void *>(&k_band_dma<10, NW, kBandLists, true>)
+    constexpr int kMaxDev = 64;
+    static uint64_t cache[kMaxDev][4];
+    const int kv = k == 1 ? 0 : k <= 4 ? 1 : k <= 10 ? 2 : 3;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return 0;
+    if (cache[dev][kv]) return cache[dev][kv];
+    const void *f = kv == 0   ? reinterpret_cast<const void *>(&k_band_dma<1, NW, kBandLists, true>)
+                    : kv == 1 ? reinterpret_cast<const void *>(&k_band_dma<4, NW, kBandLists, true>)
+                    : kv == 2 ? reinterpret_cast<const void *>(&k_band_dma<10, NW, kBandLists, true>)
                               : reinterpret_cast<const void *>(&k_band_dma<kBandK, NW, kBandLists, true>);
-    int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+    int cus = 0, per = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, 64 * NW, 0) != hipSuccess)
         return 0;
-    return (uint64_t)cus * (uint64_t)per;
+    cache[dev][kv] = (uint64_t)cus * (uint64_t)per;
+    return cache[dev][kv];
 }
 
 template <int NW>

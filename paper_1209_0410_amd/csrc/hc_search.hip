@@ -228,23 +228,29 @@ static hc_status launch_stream(const SearchArgs &a, hipStream_t st)
     return last_hip();
 }
 
-// A register list as long as k (1, 4, 10 or 16) for k <= 16, the LDS buffer
-// beyond.
 // Wavefronts of the gather kernel for k resident on the device at once
-// (compute units x wavefronts per unit; 0 if the runtime cannot say).
+// (compute units x wavefronts per unit; 0 if the runtime cannot say).  The
+// device queries run once per process, device and register-list length (a
+// racing repeat is harmless).
 static uint64_t gather_resident(uint32_t k)
 {
-    const void *f = k == 1    ? reinterpret_cast<const void *>(&k_stream<1, 1>)
-                    : k <= 4  ? reinterpret_cast<const void *>(&k_stream<4, 1>)
-                    : k <= 10 ? reinterpret_cast<const void *>(&k_stream<10, 1>)
-                    : k <= (uint32_t)kKR ? reinterpret_cast<const void *>(&k_stream<kKR, 1>)
-                                         : reinterpret_cast<const void *>(&k_stream<0, 1>);
-    int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+    constexpr int kMaxDev = 64;
+    static uint64_t cache[kMaxDev][5];
+    const int kv = k == 1 ? 0 : k <= 4 ? 1 : k <= 10 ? 2 : k <= (uint32_t)kKR ? 3 : 4;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return 0;
+    if (cache[dev][kv]) return cache[dev][kv];
+    const void *f = kv == 0   ? reinterpret_cast<const void *>(&k_stream<1, 1>)
+                    : kv == 1 ? reinterpret_cast<const void *>(&k_stream<4, 1>)
+                    : kv == 2 ? reinterpret_cast<const void *>(&k_stream<10, 1>)
+                    : kv == 3 ? reinterpret_cast<const void *>(&k_stream<kKR, 1>)
+                              : reinterpret_cast<const void *>(&k_stream<0, 1>);
+    int cus = 0, per = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, 64, 0) != hipSuccess)
         return 0;
-    return (uint64_t)cus * (uint64_t)per;
+    cache[dev][kv] = (uint64_t)cus * (uint64_t)per;
+    return cache[dev][kv];
 }
 
 // A gather search of a batch too small to keep the device's memory busy with
@@ -252,7 +258,7 @@ static uint64_t gather_resident(uint32_t k)
 // long windows (at least 4 items of slots per query) runs as work items: each
 // query's windows are cut into pieces that many wavefronts stream at once,
 // then merged (measured on MI355X: 10^3 queries at N = 5e7, w = 125,952 take
-// 41.8 ms so, 68.0 ms with one wavefront per query).
+// 41.8 ms as items against 68.0 ms with one wavefront per query).
 static bool items_route(const hc_index *idx, uint32_t nq, uint32_t k, uint64_t w,
                         size_t scratch_bytes)
 {
@@ -261,6 +267,8 @@ static bool items_route(const hc_index *idx, uint32_t nq, uint32_t k, uint64_t w
     return 3ull * nq < gather_resident(k);
 }
 
+// A register list as long as k (1, 4, 10 or 16) for k <= 16, the LDS buffer
+// beyond.
 template <int G>
 static hc_status launch_search_g(const SearchArgs &a, hipStream_t st)
 {
